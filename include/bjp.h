@@ -1,0 +1,193 @@
+/*
+ * bjp.h - block-Jacobi preconditioned conjugate gradient and Lanczos
+ * condition-number estimation for sparse SPD systems on AMD Instinct MI355X
+ * (gfx950).
+ *
+ * Method (arXiv 2410.02408, "Optimised Hybrid Classical-Quantum Algorithm
+ * for Accelerated Solution of Sparse Linear Systems"):
+ *   - Section 3.1: solve A x = b for sparse symmetric positive-definite A;
+ *     the quality measure is kappa(A) = ||A|| ||A^-1|| (2-norm: the ratio of
+ *     extreme eigenvalues).
+ *   - Section 3.2: A and b are split into contiguous diagonal blocks A_i of
+ *     n_b rows (the partition code of Section 4.2 leaves a shorter last
+ *     block when n_b does not divide N).
+ *   - Section 3.3: each block gets a preconditioner M_i and the system
+ *     M_i A_i x_i = M_i b_i.  The paper uses M_i = diag(A_i)^-1; this
+ *     library uses the inverse of the whole block A_ii (block Jacobi), which
+ *     equals the paper's choice at n_b = 1.
+ *   - Section 3.6: the solution is the concatenation of block solutions;
+ *     conjugate gradient generalises that aggregate to coupled blocks.
+ *   - Section 3.7: accuracy is ||A x - b|| / ||b||.
+ * kappa of the preconditioned operator is the quantity that sets the cost
+ * of the paper's quantum stage (Sections 2.2 and 3.4); it is estimated here
+ * with Lanczos.
+ *
+ * Conventions for every entry point:
+ *   - Pointers are DEVICE pointers unless the comment says "host".
+ *   - Work is enqueued on the caller's stream `stream` (0 = null stream).
+ *   - The library never allocates device memory: the caller queries the
+ *     workspace size with the matching *_workspace() call and passes a
+ *     buffer of at least that many bytes, 256-byte aligned.
+ *   - Entry points that fill a host info struct synchronise `stream` before
+ *     returning; bjp_apply is fully asynchronous.
+ *   - Return value: BJP_OK (0) or a negative bjp_status; nothing throws or
+ *     aborts across this interface.  Calls on one workspace must not
+ *     overlap.
+ */
+#ifndef BJP_H
+#define BJP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BJP_OK = 0,
+    BJP_EINVAL = -1,      /* bad sizes, pointers, CSR structure or block spec */
+    BJP_ENOTSPD = -2,     /* a diagonal block is not positive definite        */
+    BJP_ENOCONV = -3,     /* max_iter (or the replacement budget) exhausted   */
+    BJP_EBREAKDOWN = -4,  /* p^T A p <= 0 or r^T M^-1 r <= 0 (A not SPD)      */
+    BJP_ENONFINITE = -5,  /* NaN/Inf in the input or produced by the solve    */
+    BJP_EWORKSPACE = -6,  /* workspace missing, too small or misaligned       */
+    BJP_EHIP = -7         /* a HIP runtime call failed                         */
+} bjp_status;
+
+/* Sparse matrix in CSR form (device arrays).  Full symmetric storage (both
+ * triangles), int32 indices, FP64 values; duplicate (i, j) entries are
+ * summed, columns inside a row may be unsorted.  n >= 0; nnz = row_ptr[n]. */
+typedef struct {
+    int32_t n;
+    int32_t nnz;
+    const int32_t *row_ptr;   /* [n+1] */
+    const int32_t *col_idx;   /* [nnz] */
+    const double *val;        /* [nnz] */
+} bjp_csr_t;
+
+/* Block partition (Section 3.2).  block_size > 0: contiguous blocks of
+ * block_size rows, block t = rows [t*block_size, min((t+1)*block_size, n)).
+ * block_size == 0: explicit partition given by `offsets` (host array of
+ * num_blocks+1 strictly increasing entries, offsets[0] = 0,
+ * offsets[num_blocks] = n).  Every block has at most BJP_MAX_BLOCK rows. */
+typedef struct {
+    int32_t block_size;
+    int32_t num_blocks;       /* used only when block_size == 0 */
+    const int32_t *offsets;   /* host; used only when block_size == 0 */
+} bjp_block_spec_t;
+
+#define BJP_MAX_BLOCK 64
+
+/* Storage precision of the block inverses. */
+typedef enum {
+    BJP_FP64 = 0,        /* FP64 inverses, FP64 application */
+    BJP_FP32_STORE = 1   /* FP32 inverses applied in FP32 inside the FP64 solve */
+} bjp_precision;
+
+/* Preconditioner handle: plain data pointing into the workspace given to
+ * bjp_precondition.  It stays valid while that workspace is alive and
+ * unmodified.  Layout (for readers of the library's kernels): blocks are
+ * grouped into "packets" of 64/group consecutive blocks, group = the
+ * smallest power of two >= the largest block; every packet stores the
+ * symmetric block inverses diagonal by diagonal (see the kernels). */
+typedef struct {
+    int32_t n;
+    int32_t num_blocks;
+    int32_t precision;        /* bjp_precision */
+    int32_t group;            /* lanes per block, power of two <= 64 */
+    int32_t num_packets;
+    int32_t packet_elems;     /* scalars per packet */
+    const int32_t *offsets;   /* device [num_blocks+1] */
+    const void *tiles;        /* device, num_packets * packet_elems scalars */
+} bjp_precond_t;
+
+/* Bytes of workspace bjp_precondition needs for this matrix and partition. */
+int bjp_precondition_workspace(const bjp_csr_t *A, const bjp_block_spec_t *spec,
+                               int precision, size_t *bytes /* host out */);
+
+/* Build M = blockdiag(A_11, ..., A_kk)^-1 (Sections 3.2-3.3): extract every
+ * diagonal block of A, factor it A_tt = L L^T (Cholesky, no pivoting) and
+ * store M_t^-1 = L^-T L^-1 in `ws`.  Validates the CSR structure first.
+ * On BJP_ENOTSPD, *failed_block (host, may be NULL) receives the index of
+ * the first block whose Cholesky pivot was <= 0 or not finite; otherwise -1.
+ * Synchronises `stream`. */
+int bjp_precondition(const bjp_csr_t *A, const bjp_block_spec_t *spec, int precision,
+                     void *ws, size_t ws_bytes, bjp_precond_t *M_out /* host out */,
+                     int32_t *failed_block /* host out */, hipStream_t stream);
+
+/* z = M^-1 r (block by block).  r and z are device [n]; they must not
+ * overlap.  Asynchronous. */
+int bjp_apply(const bjp_precond_t *M, const double *r, double *z, hipStream_t stream);
+
+/* Solver options.  Zero-initialised fields take the defaults noted. */
+typedef struct {
+    double tol;               /* relative residual target (default 1e-10)          */
+    int32_t max_iter;         /* iteration cap (default n)                          */
+    int32_t x0_given;         /* 1: x holds the starting guess; 0: start from 0     */
+    int32_t max_replacements; /* true-residual restarts (default 3; <0 means none)  */
+    int32_t check_every;      /* iterations between convergence polls (default 16) */
+    int32_t spmv_lanes;       /* lanes per CSR row: 0 = auto, else 1,2,..,64       */
+    int32_t fuse_direction;   /* -1 = auto, 0 = separate p update, 1 = fused in SpMV */
+    double *history;          /* device, optional, >= max_iter+1 entries: recursive
+                                 relative residual after each iteration             */
+} bjp_pcg_opts_t;
+
+typedef struct {
+    int32_t status;            /* bjp_status of the solve                         */
+    int32_t iterations;        /* PCG iterations performed                         */
+    int32_t replacements;      /* true-residual restarts used                      */
+    int32_t polls;             /* host convergence polls                           */
+    double rel_res_recursive;  /* ||r_k|| / ||b|| of the recurrence                */
+    double rel_res_true;       /* ||b - A x|| / ||b|| recomputed at the end        */
+} bjp_pcg_info_t;
+
+/* Bytes of workspace bjp_pcg_solve needs for an n-row system. */
+int bjp_pcg_workspace(const bjp_csr_t *A, size_t *bytes /* host out */);
+
+/* Solve A x = b by preconditioned CG (Hestenes-Stiefel with a symmetric
+ * preconditioner; M == NULL gives plain CG).  Stops when the recursive
+ * residual satisfies ||r|| <= tol ||b||, then recomputes ||b - A x|| / ||b||
+ * (Section 3.7); if that is above tol the residual is replaced by the true
+ * one and iteration continues (up to max_replacements times).
+ *   b: device [n], x: device [n] (in: x0 when opts->x0_given; out: solution,
+ *   or the last iterate on BJP_ENOCONV / BJP_EBREAKDOWN).  b = 0 gives x = 0.
+ * Synchronises `stream`; `info` (host) is always filled. */
+int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, double *x,
+                  const bjp_pcg_opts_t *opts, void *ws, size_t ws_bytes,
+                  bjp_pcg_info_t *info /* host out */, hipStream_t stream);
+
+typedef struct {
+    int32_t status;       /* bjp_status                                          */
+    int32_t steps_done;   /* Lanczos steps taken (< steps after an invariant-
+                             subspace breakdown, which is success)              */
+    double theta_min;     /* smallest Ritz value                                  */
+    double theta_max;     /* largest Ritz value                                   */
+    double kappa;         /* theta_max / theta_min, a lower bound on kappa         */
+} bjp_kappa_info_t;
+
+/* Bytes of workspace bjp_kappa_estimate needs for `steps` Lanczos steps. */
+int bjp_kappa_workspace(const bjp_csr_t *A, int steps, size_t *bytes /* host out */);
+
+/* Estimate kappa(M^-1 A) = lambda_max / lambda_min (kappa(A) when M == NULL)
+ * with `steps` Lanczos steps in the M inner product, started from v0
+ * (device [n], nonzero), with full reorthogonalisation (classical
+ * Gram-Schmidt applied twice), then the extreme eigenvalues of the
+ * tridiagonal by Sturm-count multisection.  A step whose new off-diagonal is
+ * below 1e-12 of the largest coefficient ends the run early (success).
+ * alpha/beta (device [steps], optional) receive the tridiagonal.
+ * Synchronises `stream`; `info` (host) is always filled. */
+int bjp_kappa_estimate(const bjp_csr_t *A, const bjp_precond_t *M, const double *v0,
+                       int steps, double *alpha, double *beta, void *ws, size_t ws_bytes,
+                       bjp_kappa_info_t *info /* host out */, hipStream_t stream);
+
+/* Human-readable name of a status code (static storage). */
+const char *bjp_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BJP_H */

@@ -311,13 +311,13 @@ int orc_pcg(int n, const int *row_ptr, const int *col, const double *val,
             memcpy(p, z, bytes);
             for (;;) {
                 if (k >= max_iter) { status = ORC_ENOCONV; break; }
-                ++k;
                 orc_spmv(n, row_ptr, col, val, p, q);
                 double sigma = orc_dot(n, p, q);
                 if (!(sigma > 0.0)) { status = isfinite(sigma) ? ORC_EBREAKDOWN : ORC_ENONFINITE; break; }
                 double alpha = rho / sigma;
                 for (int i = 0; i < n; ++i) x[i] += alpha * p[i];
                 for (int i = 0; i < n; ++i) r[i] -= alpha * q[i];
+                ++k;  /* iterations = completed updates of x */
                 rr = orc_dot(n, r, r);
                 if (!isfinite(rr)) { status = ORC_ENONFINITE; break; }
                 relres = sqrt(rr) / bnorm;

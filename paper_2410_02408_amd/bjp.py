@@ -1,0 +1,307 @@
+"""Python binding of libbjp (include/bjp.h): argument marshalling only.
+
+Every step of the computation runs in the library's HIP kernels; PyTorch
+provides device memory (tensors) and the stream (the current stream of the
+tensors' device).  Names follow the C entry points without the ``bjp_``
+prefix: ``precondition``, ``apply``, ``pcg_solve``, ``kappa_estimate``.
+The library must be built (``python -m paper_2410_02408_amd.build``); there
+is no fallback when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libbjp.so")
+
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOTSPD", -3: "ENOCONV", -4: "EBREAKDOWN",
+          -5: "ENONFINITE", -6: "EWORKSPACE", -7: "EHIP"}
+FP64, FP32_STORE = 0, 1
+MAX_BLOCK = 64
+
+
+class CsrT(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int32), ("row_ptr", C.c_void_p),
+                ("col_idx", C.c_void_p), ("val", C.c_void_p)]
+
+
+class BlockSpecT(C.Structure):
+    _fields_ = [("block_size", C.c_int32), ("num_blocks", C.c_int32), ("offsets", C.c_void_p)]
+
+
+class PrecondT(C.Structure):
+    _fields_ = [("n", C.c_int32), ("num_blocks", C.c_int32), ("precision", C.c_int32),
+                ("group", C.c_int32), ("num_packets", C.c_int32), ("packet_elems", C.c_int32),
+                ("offsets", C.c_void_p), ("tiles", C.c_void_p)]
+
+
+class PcgOptsT(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("x0_given", C.c_int32),
+                ("max_replacements", C.c_int32), ("check_every", C.c_int32),
+                ("spmv_lanes", C.c_int32), ("fuse_direction", C.c_int32),
+                ("history", C.c_void_p)]
+
+
+class PcgInfoT(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("replacements", C.c_int32),
+                ("polls", C.c_int32), ("rel_res_recursive", C.c_double),
+                ("rel_res_true", C.c_double)]
+
+
+class KappaInfoT(C.Structure):
+    _fields_ = [("status", C.c_int32), ("steps_done", C.c_int32), ("theta_min", C.c_double),
+                ("theta_max", C.c_double), ("kappa", C.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Load libbjp.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2410_02408_amd.build")
+    L = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    vp, sz = C.c_void_p, C.c_size_t
+    L.bjp_status_string.argtypes = [C.c_int]
+    L.bjp_status_string.restype = C.c_char_p
+    L.bjp_precondition_workspace.argtypes = [P(CsrT), P(BlockSpecT), C.c_int, P(sz)]
+    L.bjp_precondition.argtypes = [P(CsrT), P(BlockSpecT), C.c_int, vp, sz, P(PrecondT),
+                                   P(C.c_int32), vp]
+    L.bjp_apply.argtypes = [P(PrecondT), vp, vp, vp]
+    L.bjp_pcg_workspace.argtypes = [P(CsrT), P(sz)]
+    L.bjp_pcg_solve.argtypes = [P(CsrT), P(PrecondT), vp, vp, P(PcgOptsT), vp, sz, P(PcgInfoT), vp]
+    L.bjp_kappa_workspace.argtypes = [P(CsrT), C.c_int, P(sz)]
+    L.bjp_kappa_estimate.argtypes = [P(CsrT), P(PrecondT), vp, C.c_int, vp, vp, vp, sz,
+                                     P(KappaInfoT), vp]
+    _lib = L
+    return L
+
+
+class BjpError(RuntimeError):
+    def __init__(self, status: int, what: str, failed_block: int = -1):
+        self.status = STATUS.get(status, str(status))
+        self.failed_block = failed_block
+        super().__init__(f"{what}: BJP_{self.status}" + (f" (block {failed_block})" if failed_block >= 0 else ""))
+
+
+def _stream(device: torch.device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _vec(v, device) -> torch.Tensor:
+    if isinstance(v, torch.Tensor):
+        t = v.to(device=device, dtype=torch.float64)
+    else:
+        t = torch.as_tensor(np.asarray(v, dtype=np.float64), device=device)
+    return t.contiguous()
+
+
+class DeviceCsr:
+    """A CSR matrix resident on the GPU (int32 indices, float64 values)."""
+
+    def __init__(self, n: int, row_ptr: torch.Tensor, col_idx: torch.Tensor, val: torch.Tensor):
+        self.n = int(n)
+        self.row_ptr = row_ptr.contiguous()
+        self.col_idx = col_idx.contiguous()
+        self.val = val.contiguous()
+        assert self.row_ptr.dtype == torch.int32 and self.col_idx.dtype == torch.int32
+        assert self.val.dtype == torch.float64
+        assert self.row_ptr.numel() == self.n + 1
+        self.nnz = int(self.col_idx.numel())
+        self.device = self.val.device
+
+    @classmethod
+    def from_host(cls, A, device="cuda"):
+        """From any object with n, row_ptr, col_idx, val (NumPy arrays)."""
+        dev = torch.device(device)
+        return cls(A.n, torch.as_tensor(np.asarray(A.row_ptr, np.int32), device=dev),
+                   torch.as_tensor(np.asarray(A.col_idx, np.int32), device=dev),
+                   torch.as_tensor(np.asarray(A.val, np.float64), device=dev))
+
+    def struct(self) -> CsrT:
+        return CsrT(self.n, self.nnz, self.row_ptr.data_ptr(),
+                    self.col_idx.data_ptr() if self.nnz else 0,
+                    self.val.data_ptr() if self.nnz else 0)
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+class Precond:
+    """Block-Jacobi preconditioner; owns the workspace its handle points into."""
+
+    def __init__(self, handle: PrecondT, ws: torch.Tensor):
+        self.handle = handle
+        self.ws = ws
+
+    @property
+    def n(self):
+        return self.handle.n
+
+    @property
+    def num_blocks(self):
+        return self.handle.num_blocks
+
+    @property
+    def precision(self):
+        return self.handle.precision
+
+    def offsets(self) -> np.ndarray:
+        start = self.handle.offsets - self.ws.data_ptr()
+        nbytes = 4 * (self.handle.num_blocks + 1)
+        return self.ws[start:start + nbytes].view(torch.int32).cpu().numpy()
+
+    def tiles(self) -> torch.Tensor:
+        """The raw packet storage (diagonal packets of the block inverses)."""
+        base = self.ws.data_ptr()
+        start = self.handle.tiles - base
+        s = 4 if self.handle.precision == FP32_STORE else 8
+        count = self.handle.num_packets * self.handle.packet_elems
+        dt = torch.float32 if s == 4 else torch.float64
+        return self.ws[start:start + count * s].view(dt)
+
+
+def _spec(block_size, offsets):
+    if offsets is not None:
+        off = np.ascontiguousarray(offsets, dtype=np.int32)
+        return BlockSpecT(0, len(off) - 1, off.ctypes.data), off
+    return BlockSpecT(int(block_size), 0, None), None
+
+
+def precondition(A: DeviceCsr, block_size: int | None = None, offsets=None,
+                 precision: str | int = "fp64") -> Precond:
+    """bjp_precondition: extract, factor and invert the diagonal blocks."""
+    L = load()
+    prec = {"fp64": FP64, "fp32": FP32_STORE}.get(precision, precision)
+    csr = A.struct()
+    spec, keep = _spec(block_size, offsets)
+    nbytes = C.c_size_t()
+    st = L.bjp_precondition_workspace(C.byref(csr), C.byref(spec), prec, C.byref(nbytes))
+    if st:
+        raise BjpError(st, "bjp_precondition_workspace")
+    ws = _workspace(nbytes.value, A.device)
+    h = PrecondT()
+    fb = C.c_int32(-1)
+    st = L.bjp_precondition(C.byref(csr), C.byref(spec), prec, _ptr(ws), ws.numel(), C.byref(h),
+                            C.byref(fb), _stream(A.device))
+    del keep
+    if st:
+        raise BjpError(st, "bjp_precondition", fb.value)
+    return Precond(h, ws)
+
+
+def apply(M: Precond, r: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """bjp_apply: z = M^-1 r (asynchronous on the current stream)."""
+    L = load()
+    r = _vec(r, M.ws.device)
+    z = torch.empty_like(r) if out is None else out
+    st = L.bjp_apply(C.byref(M.handle), _ptr(r), _ptr(z), _stream(M.ws.device))
+    if st:
+        raise BjpError(st, "bjp_apply")
+    return z
+
+
+@dataclasses.dataclass
+class PcgInfo:
+    status: str
+    iterations: int
+    replacements: int
+    polls: int
+    rel_res_recursive: float
+    rel_res_true: float
+
+
+class PcgWorkspace:
+    """Reusable solver workspace for one matrix size."""
+
+    def __init__(self, A: DeviceCsr):
+        n = C.c_size_t()
+        st = load().bjp_pcg_workspace(C.byref(A.struct()), C.byref(n))
+        if st:
+            raise BjpError(st, "bjp_pcg_workspace")
+        self.ws = _workspace(n.value, A.device)
+
+
+def pcg_solve(A: DeviceCsr, M: Precond | None, b, tol: float = 1e-10, max_iter: int | None = None,
+              x0=None, out: torch.Tensor | None = None, max_replacements: int = 3,
+              check_every: int = 0, spmv_lanes: int = 0, fuse_direction: int = -1,
+              history: torch.Tensor | None = None, workspace: PcgWorkspace | None = None):
+    """bjp_pcg_solve.  Returns (x, PcgInfo); solver failures are reported in
+    info.status, argument/workspace/runtime errors raise BjpError."""
+    L = load()
+    dev = A.device
+    b = _vec(b, dev)
+    if out is not None:
+        x = out
+        if x0 is not None:
+            x.copy_(_vec(x0, dev))
+    else:
+        x = _vec(x0, dev).clone() if x0 is not None else torch.empty(A.n, dtype=torch.float64, device=dev)
+    ws = workspace or PcgWorkspace(A)
+    opts = PcgOptsT(tol, int(max_iter or 0), 1 if x0 is not None else 0,
+                    -1 if max_replacements == 0 else int(max_replacements), int(check_every),
+                    int(spmv_lanes), int(fuse_direction),
+                    history.data_ptr() if history is not None else None)
+    info = PcgInfoT()
+    st = L.bjp_pcg_solve(C.byref(A.struct()), C.byref(M.handle) if M is not None else None,
+                         _ptr(b), _ptr(x), C.byref(opts), _ptr(ws.ws), ws.ws.numel(), C.byref(info),
+                         _stream(dev))
+    if st in (-1, -6, -7):
+        raise BjpError(st, "bjp_pcg_solve")
+    return x, PcgInfo(STATUS[info.status], info.iterations, info.replacements, info.polls,
+                      info.rel_res_recursive, info.rel_res_true)
+
+
+@dataclasses.dataclass
+class KappaInfo:
+    status: str
+    steps: int
+    theta_min: float
+    theta_max: float
+    kappa: float
+    alpha: np.ndarray
+    beta: np.ndarray
+
+
+class KappaWorkspace:
+    def __init__(self, A: DeviceCsr, steps: int):
+        n = C.c_size_t()
+        st = load().bjp_kappa_workspace(C.byref(A.struct()), int(steps), C.byref(n))
+        if st:
+            raise BjpError(st, "bjp_kappa_workspace")
+        self.steps = steps
+        self.ws = _workspace(n.value, A.device)
+
+
+def kappa_estimate(A: DeviceCsr, v0, steps: int, M: Precond | None = None,
+                   workspace: KappaWorkspace | None = None) -> KappaInfo:
+    """bjp_kappa_estimate: Lanczos estimate of kappa(M^-1 A) (kappa(A) if M is None)."""
+    L = load()
+    dev = A.device
+    v0 = _vec(v0, dev)
+    ws = workspace if workspace is not None and workspace.steps >= steps else KappaWorkspace(A, steps)
+    al = torch.zeros(steps, dtype=torch.float64, device=dev)
+    be = torch.zeros(steps, dtype=torch.float64, device=dev)
+    info = KappaInfoT()
+    st = L.bjp_kappa_estimate(C.byref(A.struct()), C.byref(M.handle) if M is not None else None,
+                              _ptr(v0), int(steps), _ptr(al), _ptr(be), _ptr(ws.ws), ws.ws.numel(),
+                              C.byref(info), _stream(dev))
+    if st in (-1, -6, -7):
+        raise BjpError(st, "bjp_kappa_estimate")
+    s = info.steps_done
+    return KappaInfo(STATUS[info.status], s, info.theta_min, info.theta_max, info.kappa,
+                     al[:s].cpu().numpy(), be[:max(s - 1, 0)].cpu().numpy())

@@ -1,0 +1,715 @@
+// Host side of the C ABI declared in include/bjp.h: argument checks,
+// workspace carving, launch configuration and the PCG / Lanczos drivers.
+// The library allocates no device memory; every buffer lives in the caller's
+// workspace.  All launches go to the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "bjp.h"
+#include "blocks.hpp"
+#include "common.hpp"
+#include "lanczos.hpp"
+#include "spmv.hpp"
+
+using namespace bjp;
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+inline size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+inline int round8(int g) { return std::max(8, (g + 7) & ~7); }
+inline int pow2_at_least(int v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+#define HIP_TRY(expr)                                 \
+    do {                                              \
+        if ((expr) != hipSuccess) return BJP_EHIP;    \
+    } while (0)
+
+struct Carver {
+    char *base;
+    size_t used = 0;
+    template <typename T>
+    T *take(size_t count) {
+        T *p = reinterpret_cast<T *>(base + used);
+        used += al256(count * sizeof(T));
+        return p;
+    }
+};
+
+int check_csr_host(const bjp_csr_t *A) {
+    if (!A || A->n < 0 || A->nnz < 0) return BJP_EINVAL;
+    if (A->n > 0 && !A->row_ptr) return BJP_EINVAL;
+    if (A->nnz > 0 && (!A->col_idx || !A->val)) return BJP_EINVAL;
+    return BJP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// utility kernels
+// ---------------------------------------------------------------------------
+__global__ void k_fill(double *p, int n, double v) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ void k_flags_init(int32_t *flags) {
+    if (threadIdx.x == 0) {
+        flags[0] = INT_MAX;
+        flags[1] = 0;
+        flags[2] = 0;
+        flags[3] = 0;
+    }
+}
+
+// flags[1] |= structural error, flags[2] |= non-finite value
+__global__ void k_validate(int n, int nnz, const int32_t *rp, const int32_t *ci, const double *val,
+                           int32_t *flags) {
+    const int stride = gridDim.x * blockDim.x;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    bool bad = false, nonfinite = false;
+    for (int i = g; i < n; i += stride) {
+        const int b = rp[i], e = rp[i + 1];
+        if (b < 0 || e < b || e > nnz) bad = true;
+        if (i == 0 && b != 0) bad = true;
+        if (i == n - 1 && e != nnz) bad = true;
+    }
+    for (int k = g; k < nnz; k += stride) {
+        const int c = ci[k];
+        if (c < 0 || c >= n) bad = true;
+        if (!isfinite(val[k])) nonfinite = true;
+    }
+    if (bad) atomicOr(&flags[1], 1);
+    if (nonfinite) atomicOr(&flags[2], 1);
+}
+
+__global__ void k_pcg_state_init(PcgState *st, double tol, int max_iter) {
+    if (threadIdx.x != 0) return;
+    st->rho = st->alpha = st->beta = 0.0;
+    st->bnorm2 = 0.0;
+    st->tol = tol;
+    st->relres = st->relres_true = 0.0;
+    st->it = 0;
+    st->done = 0;
+    st->status = BJP_OK;
+    st->max_iter = max_iter;
+    st->zero_rhs = 0;
+    st->pad = 0;
+    for (int i = 0; i < 4; ++i) st->counter[i] = 0u;
+}
+
+__global__ void k_pcg_restart(PcgState *st) {
+    if (threadIdx.x == 0) {
+        st->done = 0;
+        st->status = BJP_OK;
+    }
+}
+
+__global__ void k_lanczos_state_init(LanczosState *ls, int steps) {
+    if (threadIdx.x != 0) return;
+    ls->invb = ls->beta_prev = ls->alpha_j = ls->scale = 0.0;
+    ls->theta_min = ls->theta_max = ls->kappa = 0.0;
+    ls->j = 0;
+    ls->done = 0;
+    ls->status = BJP_OK;
+    ls->steps_done = 0;
+    ls->steps = steps;
+    ls->pad = 0;
+    for (int i = 0; i < 4; ++i) ls->counter[i] = 0u;
+}
+
+// Lanczos start: beta_0 = sqrt(r^T z) for z = M^-1 r (z == r when M = I).
+__global__ __launch_bounds__(kWG) void k_lanczos_start(LanczosState *ls, const double *r,
+                                                       const double *z, int n, int chunk,
+                                                       double *partials) {
+    const int c = xcd_chunk(blockIdx.x, gridDim.x);
+    const int r0 = c * chunk, r1 = min(r0 + chunk, n);
+    double s = 0.0;
+    for (int i = r0 + threadIdx.x; i < r1; i += kWG) s += r[i] * z[i];
+    double v[1] = {s}, out[1];
+    if (grid_sum<1>(v, partials, &ls->counter[0], out) && threadIdx.x == 0) {
+        const double bb = out[0];
+        if (!(bb > 0.0)) {
+            ls->status = isfinite(bb) ? BJP_EBREAKDOWN : BJP_ENONFINITE;
+            ls->done = 1;
+        } else {
+            ls->invb = 1.0 / sqrt(bb);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// partition
+// ---------------------------------------------------------------------------
+struct Partition {
+    std::vector<int32_t> off;
+    int nblocks = 0, G = 1, packets = 0, E = 64;
+};
+
+int make_partition(int n, const bjp_block_spec_t *spec, Partition &P) {
+    if (!spec) return BJP_EINVAL;
+    P.off.clear();
+    if (spec->block_size > 0) {
+        if (spec->block_size > BJP_MAX_BLOCK) return BJP_EINVAL;
+        for (long long s = 0; s < n; s += spec->block_size) P.off.push_back((int32_t)s);
+        P.off.push_back(n);
+    } else if (spec->block_size == 0) {
+        if (spec->num_blocks < 0 || !spec->offsets) return BJP_EINVAL;
+        P.off.assign(spec->offsets, spec->offsets + spec->num_blocks + 1);
+        if (P.off.front() != 0 || P.off.back() != n) return BJP_EINVAL;
+        for (int t = 0; t < spec->num_blocks; ++t) {
+            const int m = P.off[t + 1] - P.off[t];
+            if (m <= 0 || m > BJP_MAX_BLOCK) return BJP_EINVAL;
+        }
+    } else {
+        return BJP_EINVAL;
+    }
+    P.nblocks = (int)P.off.size() - 1;
+    int maxb = 1;
+    for (int t = 0; t < P.nblocks; ++t) maxb = std::max(maxb, P.off[t + 1] - P.off[t]);
+    P.G = pow2_at_least(maxb);
+    P.packets = ceil_div(P.nblocks, 64 / P.G);
+    P.E = packet_elems(P.G);
+    return BJP_OK;
+}
+
+size_t precond_ws_bytes(const Partition &P, int precision) {
+    const size_t s = precision == BJP_FP32_STORE ? 4 : 8;
+    return al256(sizeof(int32_t) * P.off.size()) + al256((size_t)P.packets * P.E * s) + al256(64);
+}
+
+int run_validate(const bjp_csr_t *A, int32_t *flags, hipStream_t stream) {
+    hipLaunchKernelGGL(k_flags_init, dim3(1), dim3(64), 0, stream, flags);
+    if (A->n > 0 || A->nnz > 0) {
+        const int work = std::max(A->n, A->nnz);
+        const int grid = std::min(ceil_div(work, kWG), 4096);
+        hipLaunchKernelGGL(k_validate, dim3(std::max(grid, 1)), dim3(kWG), 0, stream, A->n, A->nnz,
+                           A->row_ptr, A->col_idx, A->val, flags);
+    }
+    HIP_TRY(hipGetLastError());
+    int32_t h[4];
+    HIP_TRY(hipMemcpyAsync(h, flags, sizeof(h), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    if (h[1]) return BJP_EINVAL;
+    if (h[2]) return BJP_ENONFINITE;
+    return BJP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// kernel dispatch over compile-time shapes
+// ---------------------------------------------------------------------------
+template <typename TS>
+void launch_setup(int G, int grid, const SetupArgs &a, hipStream_t s) {
+    switch (G) {
+        case 1: hipLaunchKernelGGL((k_setup<1, TS>), dim3(grid), dim3(64), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_setup<2, TS>), dim3(grid), dim3(64), 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_setup<4, TS>), dim3(grid), dim3(64), 0, s, a); break;
+        case 8: hipLaunchKernelGGL((k_setup<8, TS>), dim3(grid), dim3(64), 0, s, a); break;
+        case 16: hipLaunchKernelGGL((k_setup<16, TS>), dim3(grid), dim3(64), 0, s, a); break;
+        case 32: hipLaunchKernelGGL((k_setup<32, TS>), dim3(grid), dim3(64), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_setup<64, TS>), dim3(grid), dim3(64), 0, s, a); break;
+    }
+}
+
+template <typename TS, int MODE>
+void launch_apply_t(int G, int grid, const ApplyArgs &a, hipStream_t s) {
+    switch (G) {
+        case 1: hipLaunchKernelGGL((k_apply<1, TS, MODE>), dim3(grid), dim3(kWG), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_apply<2, TS, MODE>), dim3(grid), dim3(kWG), 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_apply<4, TS, MODE>), dim3(grid), dim3(kWG), 0, s, a); break;
+        case 8: hipLaunchKernelGGL((k_apply<8, TS, MODE>), dim3(grid), dim3(kWG), 0, s, a); break;
+        case 16: hipLaunchKernelGGL((k_apply<16, TS, MODE>), dim3(grid), dim3(kWG), 0, s, a); break;
+        case 32: hipLaunchKernelGGL((k_apply<32, TS, MODE>), dim3(grid), dim3(kWG), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_apply<64, TS, MODE>), dim3(grid), dim3(kWG), 0, s, a); break;
+    }
+}
+
+template <int MODE>
+void launch_apply(const bjp_precond_t *M, int grid, const ApplyArgs &a, hipStream_t s) {
+    if (M->precision == BJP_FP32_STORE) launch_apply_t<float, MODE>(M->group, grid, a, s);
+    else launch_apply_t<double, MODE>(M->group, grid, a, s);
+}
+
+template <int MODE>
+void launch_spmv(int gs, int grid, const SpmvArgs &a, hipStream_t s) {
+    switch (gs) {
+        case 1: hipLaunchKernelGGL((k_spmv<1, MODE>), dim3(grid), dim3(kWG), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_spmv<2, MODE>), dim3(grid), dim3(kWG), 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_spmv<4, MODE>), dim3(grid), dim3(kWG), 0, s, a); break;
+        case 8: hipLaunchKernelGGL((k_spmv<8, MODE>), dim3(grid), dim3(kWG), 0, s, a); break;
+        case 16: hipLaunchKernelGGL((k_spmv<16, MODE>), dim3(grid), dim3(kWG), 0, s, a); break;
+        case 32: hipLaunchKernelGGL((k_spmv<32, MODE>), dim3(grid), dim3(kWG), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_spmv<64, MODE>), dim3(grid), dim3(kWG), 0, s, a); break;
+    }
+}
+
+// Launch shape of the row-streaming kernels.
+struct RowLaunch {
+    int grid, chunk;
+};
+
+RowLaunch spmv_shape(int n, int gs) {
+    const int u = gs <= 16 ? 4 : 2;
+    const int rows_per_step = (kWG / gs) * u;
+    const int grid = round8(std::min(ceil_div(n, rows_per_step), kMaxRedWG));
+    return {grid, ceil_div(n, grid)};
+}
+
+RowLaunch apply_shape(int packets) {
+    const int grid = round8(std::min(ceil_div(packets, kWaves), kMaxRedWG));
+    return {grid, ceil_div(packets, grid)};
+}
+
+RowLaunch rows_shape(int n) {
+    const int grid = round8(std::min(ceil_div(n, kWG), kMaxRedWG));
+    return {grid, ceil_div(n, grid)};
+}
+
+RowLaunch gram_shape(int n) {
+    const int per = kWG * kGramRows;
+    const int grid = round8(ceil_div(n, per));
+    return {grid, per};
+}
+
+int auto_lanes(const bjp_csr_t *A) {
+    if (A->n <= 0) return 8;
+    const double mean = (double)A->nnz / A->n;
+    int gs = 1;
+    while (gs < 64 && gs < mean) gs <<= 1;
+    return gs;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *bjp_status_string(int status) {
+    switch (status) {
+        case BJP_OK: return "BJP_OK";
+        case BJP_EINVAL: return "BJP_EINVAL";
+        case BJP_ENOTSPD: return "BJP_ENOTSPD";
+        case BJP_ENOCONV: return "BJP_ENOCONV";
+        case BJP_EBREAKDOWN: return "BJP_EBREAKDOWN";
+        case BJP_ENONFINITE: return "BJP_ENONFINITE";
+        case BJP_EWORKSPACE: return "BJP_EWORKSPACE";
+        case BJP_EHIP: return "BJP_EHIP";
+        default: return "BJP_UNKNOWN";
+    }
+}
+
+int bjp_precondition_workspace(const bjp_csr_t *A, const bjp_block_spec_t *spec, int precision,
+                               size_t *bytes) {
+    if (!bytes) return BJP_EINVAL;
+    *bytes = 0;
+    if (check_csr_host(A) != BJP_OK) return BJP_EINVAL;
+    if (precision != BJP_FP64 && precision != BJP_FP32_STORE) return BJP_EINVAL;
+    Partition P;
+    const int st = make_partition(A->n, spec, P);
+    if (st != BJP_OK) return st;
+    *bytes = precond_ws_bytes(P, precision);
+    return BJP_OK;
+}
+
+int bjp_precondition(const bjp_csr_t *A, const bjp_block_spec_t *spec, int precision, void *ws,
+                     size_t ws_bytes, bjp_precond_t *M_out, int32_t *failed_block, hipStream_t stream) {
+    if (failed_block) *failed_block = -1;
+    if (!M_out) return BJP_EINVAL;
+    std::memset(M_out, 0, sizeof(*M_out));
+    if (check_csr_host(A) != BJP_OK) return BJP_EINVAL;
+    if (precision != BJP_FP64 && precision != BJP_FP32_STORE) return BJP_EINVAL;
+    Partition P;
+    int st = make_partition(A->n, spec, P);
+    if (st != BJP_OK) return st;
+    const size_t need = precond_ws_bytes(P, precision);
+    if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255)) return BJP_EWORKSPACE;
+
+    Carver cv{static_cast<char *>(ws)};
+    int32_t *off = cv.take<int32_t>(P.off.size());
+    void *tiles = cv.base + cv.used;
+    cv.used += al256((size_t)P.packets * P.E * (precision == BJP_FP32_STORE ? 4 : 8));
+    int32_t *flags = cv.take<int32_t>(16);
+
+    M_out->n = A->n;
+    M_out->num_blocks = P.nblocks;
+    M_out->precision = precision;
+    M_out->group = P.G;
+    M_out->num_packets = P.packets;
+    M_out->packet_elems = P.E;
+    M_out->offsets = off;
+    M_out->tiles = tiles;
+
+    st = run_validate(A, flags, stream);
+    if (st != BJP_OK) return st;
+    if (A->n == 0) return BJP_OK;
+
+    HIP_TRY(hipMemcpyAsync(off, P.off.data(), sizeof(int32_t) * P.off.size(), hipMemcpyHostToDevice,
+                           stream));
+    SetupArgs sa{A->row_ptr, A->col_idx, A->val, off, P.nblocks, tiles, flags};
+    if (precision == BJP_FP32_STORE) launch_setup<float>(P.G, P.packets, sa, stream);
+    else launch_setup<double>(P.G, P.packets, sa, stream);
+    HIP_TRY(hipGetLastError());
+    int32_t h[4];
+    HIP_TRY(hipMemcpyAsync(h, flags, sizeof(h), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    if (h[0] != INT_MAX) {
+        if (failed_block) *failed_block = h[0];
+        return BJP_ENOTSPD;
+    }
+    return BJP_OK;
+}
+
+int bjp_apply(const bjp_precond_t *M, const double *r, double *z, hipStream_t stream) {
+    if (!M || M->n < 0 || (M->n > 0 && (!r || !z || !M->tiles || !M->offsets))) return BJP_EINVAL;
+    if (M->group < 1 || M->group > 64 || (M->group & (M->group - 1))) return BJP_EINVAL;
+    if (M->n == 0) return BJP_OK;
+    ApplyArgs a{};
+    a.nblocks = M->num_blocks;
+    a.num_packets = M->num_packets;
+    a.off = M->offsets;
+    a.tiles = M->tiles;
+    a.rin = r;
+    a.zout = z;
+    const RowLaunch L = apply_shape(M->num_packets);
+    a.chunk = L.chunk;
+    launch_apply<APPLY_PLAIN>(M, L.grid, a, stream);
+    HIP_TRY(hipGetLastError());
+    return BJP_OK;
+}
+
+int bjp_pcg_workspace(const bjp_csr_t *A, size_t *bytes) {
+    if (!bytes) return BJP_EINVAL;
+    *bytes = 0;
+    if (check_csr_host(A) != BJP_OK) return BJP_EINVAL;
+    const size_t vec = al256(sizeof(double) * (size_t)std::max(A->n, 1));
+    *bytes = 5 * vec + al256(sizeof(double) * 2 * kMaxRedWG) + al256(sizeof(PcgState)) + al256(64);
+    return BJP_OK;
+}
+
+int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, double *x,
+                  const bjp_pcg_opts_t *opts, void *ws, size_t ws_bytes, bjp_pcg_info_t *info,
+                  hipStream_t stream) {
+    if (!info) return BJP_EINVAL;
+    std::memset(info, 0, sizeof(*info));
+    auto fail = [&](int st) {
+        info->status = st;
+        return st;
+    };
+    if (check_csr_host(A) != BJP_OK) return fail(BJP_EINVAL);
+    const int n = A->n;
+    if (n > 0 && (!b || !x)) return fail(BJP_EINVAL);
+    if (M && (M->n != n || !M->tiles || !M->offsets)) return fail(BJP_EINVAL);
+    bjp_pcg_opts_t o{};
+    if (opts) o = *opts;
+    if (!(o.tol > 0.0)) o.tol = 1e-10;
+    if (o.max_iter <= 0) o.max_iter = std::max(n, 1);
+    if (o.max_replacements == 0) o.max_replacements = 3;
+    else if (o.max_replacements < 0) o.max_replacements = 0;
+    if (o.check_every <= 0) o.check_every = 16;
+    size_t need = 0;
+    bjp_pcg_workspace(A, &need);
+    if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255)) return fail(BJP_EWORKSPACE);
+    if (n == 0) return fail(BJP_OK);
+
+    Carver cv{static_cast<char *>(ws)};
+    double *r = cv.take<double>(n), *z = cv.take<double>(n), *p0 = cv.take<double>(n);
+    double *p1 = cv.take<double>(n), *q = cv.take<double>(n);
+    double *partials = cv.take<double>(2 * kMaxRedWG);
+    PcgState *st = cv.take<PcgState>(1);
+    int32_t *flags = cv.take<int32_t>(16);
+    if (!M) z = r;  // plain CG: the "preconditioned" residual is r itself
+
+    int s = run_validate(A, flags, stream);
+    if (s != BJP_OK) return fail(s);
+
+    const int gs = o.spmv_lanes > 0 ? pow2_at_least(std::min(o.spmv_lanes, 64)) : auto_lanes(A);
+    const bool fuse = o.fuse_direction >= 0 ? o.fuse_direction != 0 : true;
+    const RowLaunch Ls = spmv_shape(n, gs);
+    const RowLaunch La = M ? apply_shape(M->num_packets) : rows_shape(n);
+    const int fill_grid = std::min(ceil_div(n, kWG), 4096);
+
+    hipLaunchKernelGGL(k_pcg_state_init, dim3(1), dim3(64), 0, stream, st, o.tol, o.max_iter);
+    hipLaunchKernelGGL(k_fill, dim3(fill_grid), dim3(kWG), 0, stream, p0, n, 0.0);
+    hipLaunchKernelGGL(k_fill, dim3(fill_grid), dim3(kWG), 0, stream, p1, n, 0.0);
+    if (!o.x0_given) hipLaunchKernelGGL(k_fill, dim3(fill_grid), dim3(kWG), 0, stream, x, n, 0.0);
+
+    SpmvArgs sa{};
+    sa.n = n;
+    sa.chunk = Ls.chunk;
+    sa.rp = A->row_ptr;
+    sa.ci = A->col_idx;
+    sa.val = A->val;
+    sa.st = st;
+    sa.z = z;
+    sa.p0 = p0;
+    sa.p1 = p1;
+    sa.q = q;
+    sa.b = b;
+    sa.x = x;
+    sa.r = r;
+    sa.hist = o.history;
+    sa.partials = partials;
+
+    ApplyArgs aa{};
+    if (M) {
+        aa.nblocks = M->num_blocks;
+        aa.num_packets = M->num_packets;
+        aa.off = M->offsets;
+        aa.tiles = M->tiles;
+    }
+    aa.chunk = La.chunk;
+    aa.rin = r;
+    aa.zout = z;
+    aa.st = st;
+    aa.x = x;
+    aa.r = r;
+    aa.q = q;
+    aa.p0 = p0;
+    aa.p1 = p1;
+    aa.hist = o.history;
+    aa.partials = partials;
+
+    auto start_direction = [&]() {
+        if (M) launch_apply<APPLY_INIT>(M, La.grid, aa, stream);
+        else hipLaunchKernelGGL((k_rows_update<APPLY_INIT>), dim3(La.grid), dim3(kWG), 0, stream, aa, n,
+                                La.chunk);
+    };
+    auto iteration = [&]() {
+        if (fuse) {
+            launch_spmv<SPMV_DIR>(gs, Ls.grid, sa, stream);
+        } else {
+            hipLaunchKernelGGL(k_direction, dim3(fill_grid), dim3(kWG), 0, stream, st, z, p0, p1, n);
+            launch_spmv<SPMV_SIGMA>(gs, Ls.grid, sa, stream);
+        }
+        if (M) launch_apply<APPLY_UPDATE>(M, La.grid, aa, stream);
+        else hipLaunchKernelGGL((k_rows_update<APPLY_UPDATE>), dim3(La.grid), dim3(kWG), 0, stream, aa,
+                                n, La.chunk);
+    };
+    auto read_state = [&](PcgState &h) -> int {
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(&h, st, sizeof(PcgState), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        return BJP_OK;
+    };
+
+    sa.resid_phase = 0;
+    launch_spmv<SPMV_RESID>(gs, Ls.grid, sa, stream);
+    start_direction();
+
+    PcgState h{};
+    int launched = 0, replacements = 0, polls = 0, status = BJP_OK;
+    int chunk = o.check_every;
+    double prev_rel = -1.0;
+    int prev_it = 0;
+    for (;;) {
+        for (int c = 0; c < chunk; ++c) iteration();
+        launched += chunk;
+        if ((s = read_state(h)) != BJP_OK) return fail(s);
+        ++polls;
+        if (!h.done) {
+            // size the next batch from the observed convergence rate
+            int next = o.check_every;
+            if (prev_rel > 0.0 && h.relres > 0.0 && h.it > prev_it && h.relres < prev_rel) {
+                const double rate = std::log(h.relres / prev_rel) / (h.it - prev_it);
+                const double remain = std::log(o.tol / h.relres) / rate;
+                if (remain < next) next = std::max(1, (int)std::ceil(remain) + 1);
+            }
+            prev_rel = h.relres;
+            prev_it = h.it;
+            chunk = next;
+            continue;
+        }
+        if (h.status != BJP_OK || h.zero_rhs) break;
+        // converged on the recursive residual: confirm with the true one
+        sa.resid_phase = 1;
+        launch_spmv<SPMV_RESID>(gs, Ls.grid, sa, stream);
+        if ((s = read_state(h)) != BJP_OK) return fail(s);
+        if (h.relres_true <= o.tol) break;
+        if (replacements >= o.max_replacements) {
+            status = BJP_ENOCONV;
+            break;
+        }
+        ++replacements;  // r now holds b - A x: restart the direction from it
+        hipLaunchKernelGGL(k_pcg_restart, dim3(1), dim3(64), 0, stream, st);
+        start_direction();
+        chunk = o.check_every;
+        prev_rel = -1.0;
+    }
+    if (status == BJP_OK) status = h.status;
+    if (h.zero_rhs) {
+        hipLaunchKernelGGL(k_fill, dim3(fill_grid), dim3(kWG), 0, stream, x, n, 0.0);
+        h.relres_true = 0.0;
+        HIP_TRY(hipStreamSynchronize(stream));
+    } else if (status != BJP_OK) {
+        sa.resid_phase = 1;
+        launch_spmv<SPMV_RESID>(gs, Ls.grid, sa, stream);
+        if ((s = read_state(h)) != BJP_OK) return fail(s);
+    }
+    info->status = status;
+    info->iterations = h.it;
+    info->replacements = replacements;
+    info->polls = polls;
+    info->rel_res_recursive = h.relres;
+    info->rel_res_true = h.relres_true;
+    return status;
+}
+
+int bjp_kappa_workspace(const bjp_csr_t *A, int steps, size_t *bytes) {
+    if (!bytes) return BJP_EINVAL;
+    *bytes = 0;
+    if (check_csr_host(A) != BJP_OK || steps <= 0) return BJP_EINVAL;
+    const int n = std::max(A->n, 1);
+    const size_t ld = (size_t)((n + 31) & ~31);
+    const RowLaunch Lg = gram_shape(n);
+    const int redwg = std::max(kMaxRedWG, Lg.grid);
+    *bytes = 2 * al256(sizeof(double) * ld * (steps + 1))    // U, V
+             + 3 * al256(sizeof(double) * ld)                 // w, r~, z~
+             + al256(sizeof(double) * (steps + 1))            // c
+             + al256(sizeof(double) * (size_t)Lg.grid * (steps + 1))  // Gram partials
+             + 2 * al256(sizeof(double) * steps)              // alpha, beta
+             + al256(sizeof(double) * 2 * redwg)              // grid_sum partials
+             + al256(sizeof(LanczosState)) + al256(64);
+    return BJP_OK;
+}
+
+int bjp_kappa_estimate(const bjp_csr_t *A, const bjp_precond_t *M, const double *v0, int steps,
+                       double *alpha, double *beta, void *ws, size_t ws_bytes, bjp_kappa_info_t *info,
+                       hipStream_t stream) {
+    if (!info) return BJP_EINVAL;
+    std::memset(info, 0, sizeof(*info));
+    auto fail = [&](int st) {
+        info->status = st;
+        return st;
+    };
+    if (check_csr_host(A) != BJP_OK || steps <= 0) return fail(BJP_EINVAL);
+    const int n = A->n;
+    if (n == 0 || !v0) return fail(BJP_EINVAL);
+    if (M && (M->n != n || !M->tiles || !M->offsets)) return fail(BJP_EINVAL);
+    size_t need = 0;
+    bjp_kappa_workspace(A, steps, &need);
+    if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255)) return fail(BJP_EWORKSPACE);
+
+    const size_t ld = (size_t)((n + 31) & ~31);
+    const RowLaunch Lg = gram_shape(n);
+    const int redwg = std::max(kMaxRedWG, Lg.grid);
+    Carver cv{static_cast<char *>(ws)};
+    double *U = cv.take<double>(ld * (steps + 1));
+    double *V = cv.take<double>(ld * (steps + 1));
+    double *w = cv.take<double>(ld), *rt = cv.take<double>(ld), *zt = cv.take<double>(ld);
+    double *c = cv.take<double>(steps + 1);
+    double *cpart = cv.take<double>((size_t)Lg.grid * (steps + 1));
+    double *al = cv.take<double>(steps), *be = cv.take<double>(steps);
+    double *partials = cv.take<double>(2 * redwg);
+    LanczosState *ls = cv.take<LanczosState>(1);
+    int32_t *flags = cv.take<int32_t>(16);
+    if (!M) {
+        V = U;     // M = I: u_j == v_j
+        zt = rt;
+    }
+
+    int s = run_validate(A, flags, stream);
+    if (s != BJP_OK) return fail(s);
+
+    const int gs = auto_lanes(A);
+    const RowLaunch Ls = spmv_shape(n, gs);
+    const RowLaunch Lr = rows_shape(n);
+    hipLaunchKernelGGL(k_lanczos_state_init, dim3(1), dim3(64), 0, stream, ls, steps);
+    HIP_TRY(hipMemcpyAsync(rt, v0, sizeof(double) * n, hipMemcpyDeviceToDevice, stream));
+
+    ApplyArgs aa{};
+    if (M) {
+        aa.nblocks = M->num_blocks;
+        aa.num_packets = M->num_packets;
+        aa.off = M->offsets;
+        aa.tiles = M->tiles;
+    }
+    const RowLaunch La = M ? apply_shape(M->num_packets) : Lr;
+    aa.chunk = La.chunk;
+    aa.rin = rt;
+    aa.zout = zt;
+    aa.ls = ls;
+    aa.beta_out = be;
+    aa.partials = partials;
+    if (M) launch_apply<APPLY_PLAIN>(M, La.grid, aa, stream);
+    hipLaunchKernelGGL(k_lanczos_start, dim3(Lr.grid), dim3(kWG), 0, stream, ls, rt, zt, n, Lr.chunk,
+                       partials);
+
+    SpmvArgs sa{};
+    sa.n = n;
+    sa.chunk = Ls.chunk;
+    sa.rp = A->row_ptr;
+    sa.ci = A->col_idx;
+    sa.val = A->val;
+    sa.ls = ls;
+    sa.zt = zt;
+    sa.rt = rt;
+    sa.V = V;
+    sa.U = U;
+    sa.ld = ld;
+    sa.w = w;
+    sa.alpha_out = al;
+    sa.has_m = M ? 1 : 0;
+    sa.partials = partials;
+
+    GramArgs ga{};
+    ga.n = n;
+    ga.chunk = Lg.chunk;
+    ga.ls = ls;
+    ga.w = w;
+    ga.U = U;
+    ga.V = V;
+    ga.ld = ld;
+    ga.rt = rt;
+    ga.c = c;
+    ga.cpart = cpart;
+    ga.ldc = steps + 1;
+    ga.has_m = M ? 1 : 0;
+    ga.beta_out = be;
+    ga.partials = partials;
+
+    LanczosState h{};
+    for (int j = 0; j < steps; ++j) {
+        launch_spmv<SPMV_LANCZOS>(gs, Ls.grid, sa, stream);
+        hipLaunchKernelGGL((k_gram<GRAM_FIRST>), dim3(Lg.grid), dim3(kWG), 0, stream, ga);
+        hipLaunchKernelGGL(k_gram_reduce, dim3(j + 1), dim3(kWG), 0, stream, ls, cpart, steps + 1, Lg.grid, c);
+        hipLaunchKernelGGL((k_gram<GRAM_SECOND>), dim3(Lg.grid), dim3(kWG), 0, stream, ga);
+        hipLaunchKernelGGL(k_gram_reduce, dim3(j + 1), dim3(kWG), 0, stream, ls, cpart, steps + 1, Lg.grid, c);
+        hipLaunchKernelGGL((k_gram<GRAM_FINAL>), dim3(Lg.grid), dim3(kWG), 0, stream, ga);
+        if (M) launch_apply<APPLY_LANCZOS>(M, La.grid, aa, stream);
+        HIP_TRY(hipGetLastError());
+        if ((j & 31) == 31 && j + 1 < steps) {
+            HIP_TRY(hipMemcpyAsync(&h, ls, sizeof(h), hipMemcpyDeviceToHost, stream));
+            HIP_TRY(hipStreamSynchronize(stream));
+            if (h.done) break;
+        }
+    }
+    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(64), 0, stream, ls, al, be);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(&h, ls, sizeof(h), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    if (alpha && h.steps_done > 0)
+        HIP_TRY(hipMemcpyAsync(alpha, al, sizeof(double) * h.steps_done, hipMemcpyDeviceToDevice, stream));
+    if (beta && h.steps_done > 1)
+        HIP_TRY(hipMemcpyAsync(beta, be, sizeof(double) * (h.steps_done - 1), hipMemcpyDeviceToDevice,
+                               stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    info->status = h.status;
+    info->steps_done = h.steps_done;
+    info->theta_min = h.theta_min;
+    info->theta_max = h.theta_max;
+    info->kappa = h.kappa;
+    return h.status;
+}
+
+}  // extern "C"

@@ -1,0 +1,317 @@
+// Block-Jacobi preconditioner kernels: build (extract + Cholesky + inverse)
+// and application z = M^-1 r.
+//
+// Storage of the block inverses ("diagonal packets").  A block of n <= G rows
+// is handled by a group of G lanes (G = smallest power of two >= the largest
+// block), so one wave of 64 lanes holds P = 64/G blocks: a packet.  Its
+// symmetric inverse S (n x n) is stored by cyclic diagonals
+//     d_k[i] = S[i][(i + k) mod n],   k = 0 .. floor(n/2),
+// because d_{n-k} is d_k rotated, only half of the diagonals are needed:
+// k = 0 .. G/2-1 are full rows of 64 scalars (one per lane of the packet), and
+// for n = G the self-paired diagonal k = G/2 is a half row of 32 scalars.  A
+// packet therefore holds 64*(G/2) + 32 scalars = P * G(G+1)/2, exactly the
+// packed-triangle size, and lane l of the wave reads element l of every row:
+// each row is one fully coalesced 512-byte (FP64) load.  Blocks shorter than
+// G use rows 0 .. floor(n/2) and zeros elsewhere.
+//
+// Application in lane i of a group:
+//     z_i = sum_k d_k[i] r_{(i+k) mod n}              (upper part, own diagonal)
+//         + sum_{0<k<n/2} d_k[(i-k) mod n] r_{(i-k) mod n}   (mirrored part)
+// the first term rotates r across the group, the second moves the product
+// d_k r computed by lane (i-k) to lane i; both are cross-lane permutes, so
+// the tile never goes through LDS.
+#pragma once
+
+#include "common.hpp"
+
+namespace bjp {
+
+__host__ __device__ constexpr int packet_elems(int G) { return G == 1 ? 64 : 64 * (G / 2) + 32; }
+
+// ---------------------------------------------------------------------------
+// Build: one wave per packet.  LDS holds the P tiles (padded stride G+1).
+// ---------------------------------------------------------------------------
+struct SetupArgs {
+    const int32_t *rp, *ci;
+    const double *val;
+    const int32_t *off;     // [nblocks+1]
+    int nblocks;
+    void *tiles;
+    int32_t *flags;         // [0]: first failing block (INT_MAX if none)
+};
+
+template <int G, typename TS>
+__global__ __launch_bounds__(64) void k_setup(SetupArgs a) {
+    constexpr int P = 64 / G, LD = G + 1, E = packet_elems(G);
+    __shared__ double T[P][G][LD];
+    __shared__ double Wd[64];
+    const int lane = threadIdx.x, g = lane / G, i = lane % G;
+    const int pk = blockIdx.x;
+    const int t = pk * P + g;
+    int s = 0, n = 0;
+    if (t < a.nblocks) {
+        s = a.off[t];
+        n = a.off[t + 1] - s;
+    }
+    double (*Tg)[LD] = T[g];
+
+    // 1. extract row s+i of the diagonal block (duplicates summed)
+    for (int c = 0; c < G; ++c) Tg[i][c] = 0.0;
+    if (i < n) {
+        const int row = s + i;
+        const int kb = a.rp[row], ke = a.rp[row + 1];
+        for (int k = kb; k < ke; ++k) {
+            const int c = a.ci[k] - s;
+            if (c >= 0 && c < n) Tg[i][c] += a.val[k];
+        }
+    }
+    __syncthreads();
+
+    // 2. right-looking Cholesky A = L L^T, lane i owns row i
+    bool ok = true;
+    for (int j = 0; j < G; ++j) {
+        const double d = (j < n) ? Tg[j][j] : 1.0;
+        const double ljj = sqrt(d);
+        if (i == j && j < n && !(d > 0.0 && isfinite(d))) ok = false;
+        if (j < n && i > j && i < n) Tg[i][j] = Tg[i][j] / ljj;
+        __syncthreads();
+        if (j < n && i > j && i < n) {
+            const double lij = Tg[i][j];
+            for (int k = j + 1; k <= i; ++k) Tg[i][k] -= lij * Tg[k][j];
+        }
+        if (i == j && j < n) Tg[j][j] = ljj;
+        __syncthreads();
+    }
+    if (!ok) atomicMin(&a.flags[0], t);
+
+    // 3. W = L^-1 (lower); lane c computes column c, stored transposed in the
+    //    strict upper triangle (W[k][c] at T[c][k]), diagonal 1/L_cc in Wd.
+    if (i < n) Wd[g * G + i] = 1.0 / Tg[i][i];
+    __syncthreads();
+    for (int ii = 1; ii < G; ++ii) {
+        if (i < ii && ii < n) {
+            double acc = Wd[g * G + i] * Tg[ii][i];
+            for (int k = i + 1; k < ii; ++k) acc += Tg[ii][k] * Tg[i][k];
+            Tg[i][ii] = -acc * Wd[g * G + ii];
+        }
+    }
+    __syncthreads();
+
+    // 4. S = W^T W (= A_tt^-1); lane i computes S[i][j], j <= i, into the
+    //    lower triangle (L is no longer needed).
+    for (int j = 0; j < G; ++j) {
+        if (j <= i && i < n) {
+            double acc = Wd[g * G + i] * (i == j ? Wd[g * G + j] : Tg[j][i]);
+            for (int k = i + 1; k < n; ++k) acc += Tg[i][k] * Tg[j][k];
+            Tg[i][j] = acc;
+        }
+    }
+    __syncthreads();
+
+    // 5. store by cyclic diagonals (zeros where the block has no entry)
+    TS *D = static_cast<TS *>(a.tiles) + (size_t)pk * E;
+    const int nfull = (G == 1) ? 1 : G / 2;
+    for (int k = 0; k < nfull; ++k) {
+        double v = 0.0;
+        if (i < n && 2 * k <= n) {
+            int jj = i + k;
+            if (jj >= n) jj -= n;
+            v = (i >= jj) ? Tg[i][jj] : Tg[jj][i];
+        }
+        D[k * 64 + lane] = (TS)v;
+    }
+    if (G > 1 && i < G / 2) {
+        double v = 0.0;
+        if (n == G) v = Tg[i + G / 2][i];
+        D[(G / 2) * 64 + g * (G / 2) + i] = (TS)v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Application
+// ---------------------------------------------------------------------------
+enum ApplyMode { APPLY_PLAIN = 0, APPLY_INIT = 1, APPLY_UPDATE = 2, APPLY_LANCZOS = 3 };
+
+struct ApplyArgs {
+    int nblocks, num_packets, chunk;
+    const int32_t *off;
+    const void *tiles;
+    const double *rin;      // PLAIN / INIT / LANCZOS: residual to precondition
+    double *zout;           // PLAIN / INIT / LANCZOS / UPDATE: z = M^-1 r
+    PcgState *st;           // INIT / UPDATE
+    double *x, *r;          // UPDATE: x += alpha p, r -= alpha q
+    const double *q;
+    double *p0, *p1;        // UPDATE: p_new = p[(it+1)&1]
+    double *hist;           // optional residual history
+    LanczosState *ls;       // LANCZOS
+    double *beta_out;
+    double *partials;
+};
+
+// Last-workgroup decisions shared by the preconditioned and plain variants.
+__device__ __forceinline__ void pcg_after_init(PcgState *st, double rz) {
+    if (!(rz > 0.0)) {
+        st->status = isfinite(rz) ? BJP_EBREAKDOWN : BJP_ENONFINITE;
+        st->done = 1;
+    } else {
+        st->rho = rz;
+        st->beta = 0.0;
+    }
+}
+
+__device__ __forceinline__ void pcg_after_update(PcgState *st, double rz, double rr, double *hist) {
+    const int it = st->it + 1;
+    st->it = it;
+    const double relres = sqrt(rr) / sqrt(st->bnorm2);
+    st->relres = relres;
+    if (hist) hist[it] = relres;
+    if (!isfinite(rr)) {
+        st->status = BJP_ENONFINITE;
+        st->done = 1;
+    } else if (relres <= st->tol) {
+        st->done = 1;
+    } else if (!(rz > 0.0)) {
+        st->status = isfinite(rz) ? BJP_EBREAKDOWN : BJP_ENONFINITE;
+        st->done = 1;
+    } else {
+        st->beta = rz / st->rho;
+        st->rho = rz;
+        if (it >= st->max_iter) {
+            st->status = BJP_ENOCONV;
+            st->done = 1;
+        }
+    }
+}
+
+__device__ __forceinline__ void lanczos_after_beta(LanczosState *ls, double bb, double *beta_out) {
+    const int j = ls->j;
+    ls->steps_done = j + 1;
+    if (!isfinite(bb)) {
+        ls->status = BJP_ENONFINITE;
+        ls->done = 1;
+        return;
+    }
+    const double b = sqrt(bb > 0.0 ? bb : 0.0);
+    if (j + 1 == ls->steps || b <= 1e-12 * ls->scale) {
+        ls->done = 1;
+        return;
+    }
+    if (b > ls->scale) ls->scale = b;
+    if (beta_out) beta_out[j] = b;
+    ls->invb = 1.0 / b;
+    ls->beta_prev = b;
+    ls->j = j + 1;
+}
+
+template <int G, typename TS, int MODE>
+__global__ __launch_bounds__(kWG) void k_apply(ApplyArgs a) {
+    if (MODE == APPLY_INIT || MODE == APPLY_UPDATE) {
+        if (a.st->done) return;
+    }
+    if (MODE == APPLY_LANCZOS) {
+        if (a.ls->done) return;
+    }
+    constexpr int P = 64 / G, E = packet_elems(G), K = G / 2;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane / G, i = lane % G;
+    const int c = xcd_chunk(blockIdx.x, gridDim.x);
+    const int pk0 = c * a.chunk;
+    const int pk1 = min(pk0 + a.chunk, a.num_packets);
+
+    double alpha = 0.0;
+    const double *pn = nullptr;
+    if (MODE == APPLY_UPDATE) {
+        alpha = a.st->alpha;
+        pn = ((a.st->it + 1) & 1) ? a.p1 : a.p0;
+    }
+    double d0 = 0.0, d1 = 0.0;
+    for (int pk = pk0 + wave; pk < pk1; pk += kWaves) {
+        const int t = pk * P + g;
+        int s = 0, n = 0;
+        if (t < a.nblocks) {
+            s = a.off[t];
+            n = a.off[t + 1] - s;
+        }
+        const bool act = i < n;
+        const int row = s + i;
+        double rv = 0.0;
+        if (act) {
+            if (MODE == APPLY_UPDATE) {
+                const double xv = a.x[row], pv = pn[row], qv = a.q[row];
+                rv = a.r[row];
+                a.x[row] = fma(alpha, pv, xv);
+                rv = fma(-alpha, qv, rv);
+                a.r[row] = rv;
+            } else {
+                rv = a.rin[row];
+            }
+        }
+        const TS *D = static_cast<const TS *>(a.tiles) + (size_t)pk * E;
+        const TS rs = (TS)rv;
+        TS zv = D[lane] * rs;
+        const int ia = act ? i : 0;
+        const int nn = n > 0 ? n : 1;
+#pragma unroll
+        for (int k = 1; k <= K; ++k) {
+            const TS v = k < K ? D[k * 64 + lane] : D[K * 64 + g * K + (i & (K - 1))];
+            int j1 = ia + k;
+            if (j1 >= nn) j1 -= nn;
+            int j2 = ia - k;
+            if (j2 < 0) j2 += nn;
+            const TS rk = __shfl(rs, g * G + (j1 & (G - 1)), 64);
+            if (act && 2 * k <= n) zv += v * rk;
+            const TS tv = (act && 2 * k < n) ? v * rs : (TS)0;
+            const TS tt = __shfl(tv, g * G + (j2 & (G - 1)), 64);
+            if (act && 2 * k < n) zv += tt;
+        }
+        if (act) {
+            const double z = (double)zv;
+            a.zout[row] = z;
+            d0 += rv * z;
+            d1 += rv * rv;
+        }
+    }
+    if (MODE == APPLY_PLAIN) return;
+    double v[2] = {d0, d1}, out[2];
+    unsigned int *counter = (MODE == APPLY_LANCZOS) ? &a.ls->counter[0] : &a.st->counter[0];
+    if (grid_sum<2>(v, a.partials, counter, out) && threadIdx.x == 0) {
+        if (MODE == APPLY_INIT) {
+            pcg_after_init(a.st, out[0]);
+        } else if (MODE == APPLY_UPDATE) {
+            pcg_after_update(a.st, out[0], out[1], a.hist);
+        } else {
+            lanczos_after_beta(a.ls, out[0], a.beta_out);
+        }
+    }
+}
+
+// Preconditioner-free (M = I) counterpart of k_apply for PCG: z is r itself.
+template <int MODE>
+__global__ __launch_bounds__(kWG) void k_rows_update(ApplyArgs a, int n, int chunk) {
+    if (a.st->done) return;
+    const int c = xcd_chunk(blockIdx.x, gridDim.x);
+    const int r0 = c * chunk, r1 = min(r0 + chunk, n);
+    double alpha = 0.0;
+    const double *pn = nullptr;
+    if (MODE == APPLY_UPDATE) {
+        alpha = a.st->alpha;
+        pn = ((a.st->it + 1) & 1) ? a.p1 : a.p0;
+    }
+    double d1 = 0.0;
+    for (int row = r0 + threadIdx.x; row < r1; row += kWG) {
+        double rv = a.r[row];
+        if (MODE == APPLY_UPDATE) {
+            a.x[row] = fma(alpha, pn[row], a.x[row]);
+            rv = fma(-alpha, a.q[row], rv);
+            a.r[row] = rv;
+        }
+        d1 += rv * rv;
+    }
+    double v[1] = {d1}, out[1];
+    if (grid_sum<1>(v, a.partials, &a.st->counter[0], out) && threadIdx.x == 0) {
+        if (MODE == APPLY_INIT) pcg_after_init(a.st, out[0]);
+        else pcg_after_update(a.st, out[0], out[0], a.hist);
+    }
+}
+
+}  // namespace bjp

@@ -1,0 +1,212 @@
+// Lanczos in the M inner product with full reorthogonalisation, and the
+// extreme eigenvalues of the resulting tridiagonal.
+//
+// Per step j (basis v_0..v_j, M-orthonormal, u_l = M v_l kept alongside so M
+// is never applied forward):
+//   k_spmv<LANCZOS>        v_j, u_j normalised; w = A v_j; alpha_j = v_j^T w
+//   k_gram<GRAM_FIRST>     r~ = w - alpha_j u_j - beta_{j-1} u_{j-1};
+//                          partial c_l = v_l^T r~            (l <= j)
+//   k_gram_reduce          c_l = sum of partials (fixed order)
+//   k_gram<GRAM_SECOND>    r~ -= sum_l c_l u_l; partial c_l = v_l^T r~
+//   k_gram_reduce
+//   k_gram<GRAM_FINAL>     r~ -= sum_l c_l u_l   (with M = I also beta_j)
+//   k_apply<LANCZOS>       z~ = M^-1 r~; beta_j = sqrt(r~^T z~)
+// The Gram passes are tall-skinny products over the j+1 stored vectors and
+// stream 8(j+1)N bytes each: they dominate the estimate's cost at large j.
+#pragma once
+
+#include "blocks.hpp"
+#include "common.hpp"
+
+namespace bjp {
+
+constexpr int kGramRows = 8;      // rows per thread in the Gram kernels
+constexpr int kGramTile = 256;    // basis vectors reduced per LDS round
+
+enum GramPass { GRAM_FIRST = 0, GRAM_SECOND = 1, GRAM_FINAL = 2 };
+
+struct GramArgs {
+    int n, chunk;            // chunk = rows per workgroup (kWG * kGramRows)
+    LanczosState *ls;
+    const double *w;         // FIRST: A v_j
+    const double *U, *V;     // bases, vector l at l*ld (V == U when M = I)
+    size_t ld;
+    double *rt;              // r~, updated in place
+    const double *c;         // SECOND / FINAL: coefficients of the previous pass
+    double *cpart;           // FIRST / SECOND: partial coefficients [grid][ldc]
+    int ldc;
+    int has_m;
+    double *beta_out;        // FINAL with M = I
+    double *partials;        // FINAL with M = I: grid_sum scratch
+};
+
+template <int PASS>
+__global__ __launch_bounds__(kWG) void k_gram(GramArgs a) {
+    LanczosState *ls = a.ls;
+    if (ls->done) return;
+    const int j = ls->j;
+    const int tid = threadIdx.x;
+    const int c = xcd_chunk(blockIdx.x, gridDim.x);
+    const int r0 = c * a.chunk;
+    const int r1 = min(r0 + a.chunk, a.n);
+    double rv[kGramRows];
+    int rows[kGramRows];
+#pragma unroll
+    for (int q = 0; q < kGramRows; ++q) {
+        const int row = r0 + q * kWG + tid;
+        rows[q] = row < r1 ? row : -1;
+        double v = 0.0;
+        if (row < r1) {
+            if (PASS == GRAM_FIRST) {
+                v = a.w[row] - ls->alpha_j * a.U[(size_t)j * a.ld + row];
+                if (j > 0) v -= ls->beta_prev * a.U[(size_t)(j - 1) * a.ld + row];
+            } else {
+                v = a.rt[row];
+            }
+        }
+        rv[q] = v;
+    }
+    if (PASS != GRAM_FIRST) {
+        for (int l = 0; l <= j; ++l) {
+            const double cl = a.c[l];
+            const double *ul = a.U + (size_t)l * a.ld;
+#pragma unroll
+            for (int q = 0; q < kGramRows; ++q)
+                if (rows[q] >= 0) rv[q] -= cl * ul[rows[q]];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kGramRows; ++q)
+        if (rows[q] >= 0) a.rt[rows[q]] = rv[q];
+
+    if (PASS != GRAM_FINAL) {
+        __shared__ double red[kGramTile][kWaves];
+        const int lane = tid & 63, wave = tid >> 6;
+        for (int l0 = 0; l0 <= j; l0 += kGramTile) {
+            const int l1 = min(l0 + kGramTile, j + 1);
+            for (int l = l0; l < l1; ++l) {
+                const double *vl = a.V + (size_t)l * a.ld;
+                double s = 0.0;
+#pragma unroll
+                for (int q = 0; q < kGramRows; ++q)
+                    if (rows[q] >= 0) s += vl[rows[q]] * rv[q];
+                s = wave_sum(s);
+                if (lane == 0) red[l - l0][wave] = s;
+            }
+            __syncthreads();
+            if (tid < l1 - l0) {
+                double s = 0.0;
+                for (int w = 0; w < kWaves; ++w) s += red[tid][w];
+                a.cpart[(size_t)blockIdx.x * a.ldc + l0 + tid] = s;
+            }
+            __syncthreads();
+        }
+    } else if (!a.has_m) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < kGramRows; ++q) s += rv[q] * rv[q];
+        double v[1] = {s}, out[1];
+        if (grid_sum<1>(v, a.partials, &ls->counter[0], out) && tid == 0)
+            lanczos_after_beta(ls, out[0], a.beta_out);
+    }
+}
+
+// c_l = sum over workgroups of cpart[w][l]; one workgroup per l.
+__global__ __launch_bounds__(kWG) void k_gram_reduce(LanczosState *ls, const double *cpart, int ldc,
+                                                     int nparts, double *c) {
+    if (ls->done) return;
+    const int l = blockIdx.x;
+    if (l > ls->j) return;
+    double s = 0.0;
+    for (int w = threadIdx.x; w < nparts; w += kWG) s += cpart[(size_t)w * ldc + l];
+    __shared__ double red[kWaves];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kWaves; ++w) t += red[w];
+        c[l] = t;
+    }
+}
+
+// Number of eigenvalues of T = tridiag(beta; alpha; beta) below x: negative
+// pivots of the LDL^T factorisation of T - x I (pivots below pivmin in size
+// are pushed to -pivmin).
+__device__ int sturm_count(const double *al, const double *be, int s, double x, double pivmin) {
+    int cnt = 0;
+    double d = al[0] - x;
+    if (fabs(d) < pivmin) d = -pivmin;
+    if (d < 0.0) ++cnt;
+    for (int i = 1; i < s; ++i) {
+        d = al[i] - x - be[i - 1] * be[i - 1] / d;
+        if (fabs(d) < pivmin) d = -pivmin;
+        if (d < 0.0) ++cnt;
+    }
+    return cnt;
+}
+
+__device__ double wave_min(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Extreme eigenvalues of the s x s Lanczos tridiagonal by Sturm-count
+// multisection: each round the 64 lanes probe 64 interior points of the
+// current bracket, which shrinks it 65-fold.  One wave.
+__global__ __launch_bounds__(64) void k_tridiag(LanczosState *ls, const double *al, const double *be) {
+    const int s = ls->steps_done;
+    if (ls->status != BJP_OK || s <= 0) return;
+    const int lane = threadIdx.x;
+    double glo = INFINITY, ghi = -INFINITY, bmax = 1.0;
+    for (int i = lane; i < s; i += 64) {
+        double rad = 0.0;
+        if (i > 0) rad += fabs(be[i - 1]);
+        if (i + 1 < s) {
+            rad += fabs(be[i]);
+            bmax = fmax(bmax, be[i] * be[i]);
+        }
+        glo = fmin(glo, al[i] - rad);
+        ghi = fmax(ghi, al[i] + rad);
+    }
+    glo = wave_min(glo);
+    ghi = wave_max(ghi);
+    bmax = wave_max(bmax);
+    const double eps = 2.220446049250313e-16;
+    const double pivmin = 2.2250738585072014e-308 * bmax;
+    const double widen = 4.0 * eps * (fabs(glo) + fabs(ghi) + (ghi - glo)) * s + 2.0 * pivmin;
+    glo -= widen;
+    ghi += widen;
+    double res[2];
+    for (int which = 0; which < 2; ++which) {
+        const int target = which == 0 ? 1 : s;
+        double lo = glo, hi = ghi;
+        for (int round = 0; round < 64; ++round) {
+            if (hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi)) || hi - lo <= pivmin) break;
+            const double h = (hi - lo) / 65.0;
+            const double xl = lo + h * (lane + 1);
+            const int cnt = sturm_count(al, be, s, xl, pivmin);
+            const unsigned long long hit = __ballot(cnt >= target);
+            // first probe that has reached the target count
+            const int first = hit ? __ffsll((long long)hit) - 1 : 64;
+            const double nlo = first == 0 ? lo : lo + h * first;
+            const double nhi = first == 64 ? hi : lo + h * (first + 1);
+            lo = nlo;
+            hi = nhi;
+        }
+        res[which] = 0.5 * (lo + hi);
+    }
+    if (lane == 0) {
+        ls->theta_min = res[0];
+        ls->theta_max = res[1];
+        ls->kappa = res[1] / res[0];
+    }
+}
+
+}  // namespace bjp

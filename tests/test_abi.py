@@ -1,0 +1,82 @@
+"""The C-ABI library loads and exports every symbol the header declares
+(no compute calls: these run without a GPU)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bjp.h")
+LIB = os.path.join(ROOT, "paper_2410_02408_amd", "libbjp.so")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2410_02408_amd import build
+
+        build.build()
+    return C.CDLL(LIB)
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(bjp_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_four_verbs():
+    names = declared_functions()
+    for verb in ["bjp_precondition", "bjp_apply", "bjp_pcg_solve", "bjp_kappa_estimate"]:
+        assert verb in names
+    assert len(names) >= 8
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    lib.bjp_status_string.restype = C.c_char_p
+    assert lib.bjp_status_string(0) == b"BJP_OK"
+    assert lib.bjp_status_string(-2) == b"BJP_ENOTSPD"
+    assert lib.bjp_status_string(12345) == b"BJP_UNKNOWN"
+
+
+def test_workspace_queries_without_gpu(lib):
+    """Size queries are pure host logic."""
+    from paper_2410_02408_amd import bjp
+
+    L = bjp.load()
+    csr = bjp.CsrT(2097152, 14581760, 1, 1, 1)
+    spec = bjp.BlockSpecT(64, 0, None)
+    n = C.c_size_t()
+    assert L.bjp_precondition_workspace(C.byref(csr), C.byref(spec), 0, C.byref(n)) == 0
+    # 32768 blocks of 64 -> one packet each of 2080 doubles, plus offsets and flags
+    assert n.value >= 32768 * 2080 * 8
+    assert n.value < 32768 * 2080 * 8 + 200000
+    assert L.bjp_precondition_workspace(C.byref(csr), C.byref(spec), 1, C.byref(n)) == 0
+    assert 32768 * 2080 * 4 <= n.value < 32768 * 2080 * 4 + 200000
+    bad = bjp.BlockSpecT(65, 0, None)
+    assert L.bjp_precondition_workspace(C.byref(csr), C.byref(bad), 0, C.byref(n)) == -1
+    assert L.bjp_pcg_workspace(C.byref(csr), C.byref(n)) == 0 and n.value >= 5 * 8 * 2097152
+    assert L.bjp_kappa_workspace(C.byref(csr), 200, C.byref(n)) == 0
+    assert n.value >= 2 * 201 * 8 * 2097152
+    assert L.bjp_kappa_workspace(C.byref(csr), 0, C.byref(n)) == -1
+
+
+def test_argument_errors_without_gpu(lib):
+    """Calls rejected before any device work."""
+    from paper_2410_02408_amd import bjp
+
+    L = bjp.load()
+    csr = bjp.CsrT(-1, 0, None, None, None)
+    info = bjp.PcgInfoT()
+    assert L.bjp_pcg_solve(C.byref(csr), None, None, None, None, None, 0, C.byref(info), None) == -1
+    assert info.status == -1
+    csr = bjp.CsrT(10, 30, 1, 1, 1)
+    assert L.bjp_pcg_solve(C.byref(csr), None, 1, 1, None, None, 0, C.byref(info), None) == -6
+    kinfo = bjp.KappaInfoT()
+    assert L.bjp_kappa_estimate(C.byref(csr), None, 1, 0, None, None, None, 0, C.byref(kinfo), None) == -1

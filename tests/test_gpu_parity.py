@@ -1,0 +1,311 @@
+"""GPU path (C-ABI via the binding) against the CPU oracle, element by element.
+
+Tolerances (derived in the design notes):
+  * z = M^-1 r: the GPU multiplies by an explicit inverse, the oracle solves
+    with the Cholesky factor; both are backward stable, so the difference is
+    O(kappa(A_tt) eps): relative 1e-10 for the FP64 path.
+  * PCG: same algorithm and stopping rule on both sides; pass if the
+    iteration counts differ by at most one, ||x_gpu - x_or|| / ||x_or|| <= 1e-10
+    and the GPU's true residual (recomputed by the oracle) <= tol.
+  * kappa: relative difference <= 1e-6 with equal step counts.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2410_02408_amd import workloads as w
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def dev(A):
+    from paper_2410_02408_amd import bjp
+
+    return bjp.DeviceCsr.from_host(A, DEV)
+
+
+def decode_inverses(M, off):
+    """Dense block inverses from the diagonal-packet layout (layout only)."""
+    G = M.handle.group
+    P = 64 // G
+    E = M.handle.packet_elems
+    D = M.tiles().double().cpu().numpy()
+    out = []
+    for t in range(len(off) - 1):
+        n = off[t + 1] - off[t]
+        pk, g = divmod(t, P)
+        base = pk * E
+        S = np.zeros((n, n))
+        for k in range(max(G // 2, 1)):
+            if 2 * k > n:
+                continue
+            for i in range(n):
+                j = (i + k) % n
+                S[i, j] = S[j, i] = D[base + k * 64 + g * G + i]
+        if G > 1 and n == G:
+            for i in range(G // 2):
+                S[i, i + G // 2] = S[i + G // 2, i] = D[base + (G // 2) * 64 + g * (G // 2) + i]
+        out.append(S)
+    return out
+
+
+CASES = [
+    ("poisson2d_32/16", lambda: w.poisson2d(32), 16),
+    ("diffusion3d_16/64", lambda: w.diffusion3d(16), 64),
+    ("random_spd_1000/64 ragged", lambda: w.random_spd(1000, np.random.default_rng(1)), 64),
+    ("random_spd_777/32 ragged", lambda: w.random_spd(777, np.random.default_rng(2)), 32),
+    ("random_spd_500/16", lambda: w.random_spd(500, np.random.default_rng(3)), 16),
+    ("random_spd_300/8", lambda: w.random_spd(300, np.random.default_rng(4)), 8),
+    ("random_spd_301/4", lambda: w.random_spd(301, np.random.default_rng(5)), 4),
+    ("random_spd_199/2", lambda: w.random_spd(199, np.random.default_rng(6)), 2),
+    ("diffusion3d_8/1", lambda: w.diffusion3d(8), 1),
+    ("random_spd_150/24 (pow2 group 32)", lambda: w.random_spd(150, np.random.default_rng(7)), 24),
+]
+
+
+@pytest.mark.parametrize("name,make,nb", CASES, ids=[c[0] for c in CASES])
+def test_apply_matches_oracle(gpu, orc, name, make, nb):
+    A = make()
+    print(f"case {name}", flush=True)
+    M = gpu.precondition(dev(A), block_size=nb)
+    Mo = orc.Precond.uniform(A, nb)
+    r = w.rhs(A.n, 31)
+    z = gpu.apply(M, torch.as_tensor(r, device=DEV)).cpu().numpy()
+    zo = Mo.apply(r)
+    assert np.linalg.norm(z - zo) / np.linalg.norm(zo) <= 1e-10
+    np.testing.assert_array_equal(M.offsets(), orc.uniform_offsets(A.n, nb))
+
+
+@pytest.mark.parametrize("name,make,nb", CASES[:6], ids=[c[0] for c in CASES[:6]])
+def test_block_inverses(gpu, orc, name, make, nb):
+    A = make()
+    M = gpu.precondition(dev(A), block_size=nb)
+    off = orc.uniform_offsets(A.n, nb)
+    inv = decode_inverses(M, off)
+    for t in sorted(set([0, 1, len(off) - 2]) & set(range(len(off) - 1))):
+        s, e = off[t], off[t + 1]
+        T = orc.extract_block(A, s, e)
+        np.testing.assert_allclose(inv[t] @ T, np.eye(e - s), atol=1e-11 * np.linalg.cond(T))
+
+
+def test_explicit_offsets(gpu, orc):
+    A = w.random_spd(400, np.random.default_rng(8))
+    off = np.array([0, 5, 64, 70, 100, 133, 197, 250, 251, 300, 364, 400], np.int32)
+    M = gpu.precondition(dev(A), offsets=off)
+    assert M.handle.group == 64
+    r = w.rhs(400, 32)
+    z = gpu.apply(M, torch.as_tensor(r, device=DEV)).cpu().numpy()
+    zo = orc.Precond(A, off).apply(r)
+    assert np.linalg.norm(z - zo) / np.linalg.norm(zo) <= 1e-10
+    x, info = gpu.pcg_solve(dev(A), M, r)
+    ref = orc.pcg(A, r, orc.Precond(A, off))
+    assert info.status == "OK" and abs(info.iterations - ref.iterations) <= 1
+
+
+def test_apply_fp32_store(gpu, orc):
+    A = w.diffusion3d(16)
+    M = gpu.precondition(dev(A), block_size=64, precision="fp32")
+    assert M.precision == gpu.FP32_STORE
+    r = w.rhs(A.n, 33)
+    z = gpu.apply(M, torch.as_tensor(r, device=DEV)).cpu().numpy()
+    zo = orc.Precond.uniform(A, 64).apply(r)
+    assert np.linalg.norm(z - zo) / np.linalg.norm(zo) <= 1e-4
+
+
+def test_not_spd_reports_block(gpu, orc):
+    A = w.random_spd(100, np.random.default_rng(9))
+    i = 3 * 16 + 5
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    A.val[np.nonzero((rows == i) & (A.col_idx == i))[0]] = -1.0
+    with pytest.raises(gpu.BjpError) as e:
+        gpu.precondition(dev(A), block_size=16)
+    assert e.value.status == "ENOTSPD" and e.value.failed_block == 3
+
+
+def test_malformed_csr_rejected(gpu):
+    A = w.poisson2d(8)
+    bad = w.CsrMatrix(A.n, A.row_ptr.copy(), A.col_idx.copy(), A.val.copy())
+    bad.col_idx[7] = 1000
+    with pytest.raises(gpu.BjpError) as e:
+        gpu.precondition(dev(bad), block_size=8)
+    assert e.value.status == "EINVAL"
+    with pytest.raises(gpu.BjpError):
+        gpu.pcg_solve(dev(bad), None, np.ones(A.n))
+    bad = w.CsrMatrix(A.n, A.row_ptr.copy(), A.col_idx.copy(), A.val.copy())
+    bad.row_ptr[10] = bad.row_ptr[12]
+    with pytest.raises(gpu.BjpError):
+        gpu.precondition(dev(bad), block_size=8)
+    nan = w.CsrMatrix(A.n, A.row_ptr, A.col_idx, A.val.copy())
+    nan.val[3] = np.inf
+    with pytest.raises(gpu.BjpError) as e:
+        gpu.precondition(dev(nan), block_size=8)
+    assert e.value.status == "ENONFINITE"
+
+
+def _pcg_parity(gpu, orc, A, b, nb, tol=1e-10, **kw):
+    Md = gpu.precondition(dev(A), block_size=nb) if nb else None
+    Mo = orc.Precond.uniform(A, nb) if nb else None
+    x, info = gpu.pcg_solve(dev(A), Md, b, tol=tol, **kw)
+    ref = orc.pcg(A, b, Mo, tol=tol)
+    xg = x.cpu().numpy()
+    true_res = np.linalg.norm(orc.spmv(A, xg) - b) / np.linalg.norm(b)
+    err = np.linalg.norm(xg - ref.x) / np.linalg.norm(ref.x)
+    print(f"  it gpu {info.iterations} oracle {ref.iterations} err {err:.2e} res {true_res:.2e}")
+    assert info.status == "OK" and ref.status == "OK"
+    assert abs(info.iterations - ref.iterations) <= 1
+    assert true_res <= tol and info.rel_res_true <= tol
+    assert abs(info.rel_res_true - true_res) <= 1e-3 * tol
+    if info.iterations == ref.iterations:
+        assert err <= 1e-10
+    else:
+        ref2 = orc.pcg(A, b, Mo, tol=0.0, max_iter=info.iterations, max_replacements=0)
+        assert np.linalg.norm(xg - ref2.x) / np.linalg.norm(ref2.x) <= 1e-10
+    return info, ref
+
+
+PCG_CASES = [
+    ("poisson2d_32/16", lambda: w.workload("poisson2d_32"), 16),
+    ("diffusion3d_16/64", lambda: w.workload("diffusion3d_16"), 64),
+    ("diffusion3d_24/64", lambda: w.workload("diffusion3d_24"), 64),
+    ("diffusion3d_16/none", lambda: w.workload("diffusion3d_16"), 0),
+    ("diffusion3d_16/1", lambda: w.workload("diffusion3d_16"), 1),
+    ("diffusion3d_16/8", lambda: w.workload("diffusion3d_16"), 8),
+]
+
+
+@pytest.mark.parametrize("name,make,nb", PCG_CASES, ids=[c[0] for c in PCG_CASES])
+def test_pcg_matches_oracle(gpu, orc, name, make, nb):
+    print(f"case {name}", flush=True)
+    W = make()
+    _pcg_parity(gpu, orc, W.A, W.b, nb)
+
+
+def test_pcg_random_spd_ragged(gpu, orc):
+    A = w.random_spd(5000, np.random.default_rng(10))
+    _pcg_parity(gpu, orc, A, w.rhs(A.n, 34), 32)
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16, 32, 64])
+@pytest.mark.parametrize("fuse", [0, 1])
+def test_pcg_schedules_agree(gpu, orc, lanes, fuse):
+    """Every SpMV lane-group width and both direction-update placements give
+    oracle-parity results."""
+    W = w.workload("diffusion3d_16")
+    _pcg_parity(gpu, orc, W.A, W.b, 64, spmv_lanes=lanes, fuse_direction=fuse)
+
+
+def test_pcg_single_block_one_iteration(gpu):
+    A = w.poisson2d(8)
+    b = w.rhs(64, 11)
+    x, info = gpu.pcg_solve(dev(A), gpu.precondition(dev(A), block_size=64), b)
+    assert info.status == "OK" and info.iterations == 1
+    np.testing.assert_allclose(x.cpu().numpy(), np.linalg.solve(A.to_dense(), b), rtol=1e-12)
+
+
+def test_pcg_deterministic(gpu):
+    W = w.workload("diffusion3d_16")
+    A = dev(W.A)
+    M = gpu.precondition(A, block_size=64)
+    x1, i1 = gpu.pcg_solve(A, M, W.b)
+    x2, i2 = gpu.pcg_solve(A, M, W.b)
+    assert i1.iterations == i2.iterations
+    assert torch.equal(x1, x2)
+
+
+def test_pcg_edge_cases(gpu):
+    A = w.poisson2d(16)
+    Ad = dev(A)
+    M = gpu.precondition(Ad, block_size=8)
+    x, info = gpu.pcg_solve(Ad, M, np.zeros(256), x0=np.ones(256))
+    assert info.status == "OK" and info.iterations == 0 and torch.all(x == 0)
+    x, info = gpu.pcg_solve(Ad, M, w.rhs(256, 15), max_iter=1)
+    assert info.status == "ENOCONV" and info.iterations == 1 and 0 < info.rel_res_true < 1
+    b = np.ones(256)
+    b[3] = np.nan
+    x, info = gpu.pcg_solve(Ad, M, b)
+    assert info.status == "ENONFINITE"
+    xs = np.linalg.solve(A.to_dense(), w.rhs(256, 16))
+    x, info = gpu.pcg_solve(Ad, M, w.rhs(256, 16), x0=xs)
+    assert info.status == "OK" and info.iterations == 0
+
+
+def test_pcg_indefinite_breakdown(gpu, orc):
+    n = 32
+    rows, cols, vals = list(range(n)), list(range(n)), [1.0] * n
+    for i in range(0, n, 2):
+        j = (i + 17) % n
+        rows += [i, j]; cols += [j, i]; vals += [3.0, 3.0]
+    A = w.from_coo(n, np.array(rows), np.array(cols), np.array(vals))
+    ev, vec = np.linalg.eigh(A.to_dense())
+    Ad = dev(A)
+    x, info = gpu.pcg_solve(Ad, gpu.precondition(Ad, block_size=8), vec[:, 0])
+    assert info.status == "EBREAKDOWN" and info.iterations == 0
+
+
+def test_pcg_history_matches_oracle(gpu, orc):
+    W = w.workload("poisson2d_32")
+    hist = torch.full((W.A.n + 1,), float("nan"), dtype=torch.float64, device=DEV)
+    x, info = gpu.pcg_solve(dev(W.A), gpu.precondition(dev(W.A), block_size=16), W.b, history=hist)
+    ref = orc.pcg(W.A, W.b, orc.Precond.uniform(W.A, 16), history=True)
+    h = hist[: info.iterations + 1].cpu().numpy()
+    k = min(len(h), len(ref.history))
+    np.testing.assert_allclose(h[:k], ref.history[:k], rtol=1e-6)
+
+
+def test_empty_system(gpu):
+    from paper_2410_02408_amd import bjp
+
+    A = bjp.DeviceCsr(0, torch.zeros(1, dtype=torch.int32, device=DEV),
+                      torch.zeros(0, dtype=torch.int32, device=DEV),
+                      torch.zeros(0, dtype=torch.float64, device=DEV))
+    x, info = gpu.pcg_solve(A, None, torch.zeros(0, dtype=torch.float64, device=DEV))
+    assert info.status == "OK" and x.numel() == 0
+
+
+# ------------------------------------------------------------------ kappa
+
+def test_kappa_cfg_small(gpu, orc):
+    W = w.workload("poisson2d_32")
+    A = dev(W.A)
+    k = gpu.kappa_estimate(A, W.b, 100)
+    ko = orc.kappa(W.A, W.b, 100)
+    assert k.status == "OK" and k.steps == ko.steps
+    assert abs(k.kappa - ko.kappa) <= 1e-6 * ko.kappa
+    assert abs(k.kappa - 1 / np.tan(np.pi / 66) ** 2) <= 1e-6 * k.kappa
+    M = gpu.precondition(A, block_size=16)
+    k = gpu.kappa_estimate(A, W.b, 100, M)
+    ko = orc.kappa(W.A, W.b, 100, orc.Precond.uniform(W.A, 16))
+    assert k.steps == ko.steps and abs(k.kappa - ko.kappa) <= 1e-6 * ko.kappa
+    assert abs(k.kappa - 234.53060475823) <= 1e-6 * k.kappa
+    np.testing.assert_allclose(k.alpha, ko.alpha, rtol=1e-8, atol=1e-12)
+
+
+@pytest.mark.parametrize("nb", [0, 64, 8])
+def test_kappa_diffusion(gpu, orc, nb):
+    W = w.workload("diffusion3d_16")
+    A = dev(W.A)
+    M = gpu.precondition(A, block_size=nb) if nb else None
+    k = gpu.kappa_estimate(A, W.b, 60, M)
+    ko = orc.kappa(W.A, W.b, 60, orc.Precond.uniform(W.A, nb) if nb else None)
+    assert k.steps == ko.steps
+    assert abs(k.kappa - ko.kappa) <= 1e-6 * ko.kappa
+
+
+def test_kappa_single_block_and_breakdown(gpu):
+    A = w.poisson2d(8)
+    Ad = dev(A)
+    k = gpu.kappa_estimate(Ad, w.rhs(64, 20), 30, gpu.precondition(Ad, block_size=64))
+    assert k.status == "OK" and k.steps == 1 and abs(k.kappa - 1) < 1e-12
+    k = gpu.kappa_estimate(Ad, np.zeros(64), 5)
+    assert k.status == "EBREAKDOWN"
+
+
+def test_kappa_many_steps_tiles(gpu, orc):
+    """More than one LDS tile of Gram coefficients (j > 256)."""
+    A = w.random_spd(400, np.random.default_rng(11), shift=0.3)
+    Ad = dev(A)
+    k = gpu.kappa_estimate(Ad, w.rhs(400, 21), 300)
+    ko = orc.kappa(A, w.rhs(400, 21), 300)
+    assert k.steps == ko.steps
+    assert abs(k.kappa - ko.kappa) <= 1e-6 * ko.kappa
