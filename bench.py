@@ -1,0 +1,207 @@
+"""Benchmark: block-Jacobi PCG + Lanczos kappa on one MI355X.
+
+One step = the whole hot path over one synthetic system already resident in
+HBM: CSR validation and block extraction + batched Cholesky inversion
+(bjp_precondition), PCG to a 1e-10 relative residual (bjp_pcg_solve), and the
+Lanczos estimates kappa(A) and kappa(M^-1 A) (bjp_kappa_estimate, twice).
+
+Headline value: PCG iterations per second over the timed solves.  The line
+also carries the roofline of the dominant kernel (the block-inverse
+application, timed live with HIP events around each of its launches) and the
+CPU oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--workload diffusion3d_128]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="diffusion3d_128")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=40)
+    ap.add_argument("--kappa-steps", type=int, default=0, help="override Lanczos steps (0 = workload's)")
+    return ap.parse_args()
+
+
+def apply_bytes(n: int, offsets, elem: int) -> int:
+    """Algorithmic bytes of one block-apply launch inside PCG: the packed
+    block inverses (sum_t n_t(n_t+1)/2 scalars), the block offsets, and the
+    vectors x, p, r, q read (32 N) and x, r, z written (24 N)."""
+    import numpy as np
+
+    nt = np.diff(np.asarray(offsets, dtype=np.int64))
+    return int(elem * np.sum(nt * (nt + 1) // 2) + 4 * len(offsets) + 56 * n)
+
+
+def spmv_bytes(n: int, nnz: int) -> int:
+    """Algorithmic bytes of one fused SpMV launch: CSR (12 nnz + 4(N+1)),
+    z and p_old read (16 N), p_new and q written (16 N)."""
+    return 12 * nnz + 4 * (n + 1) + 32 * n
+
+
+def read_traffic(kernel_tag: str):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_counters.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"source_sha256:\s*([0-9a-f]+)", text)
+    t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m or not t:
+        return None
+    from paper_2410_02408_amd import build
+
+    if m.group(1) != build.source_digest():
+        return None
+    return float(t.group(1))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+              "(the solver runs on a single MI355X).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2410_02408_amd import bjp, workloads
+
+    t0 = time.time()
+    W = workloads.workload(args.workload)
+    gen_s = time.time() - t0
+    steps_k = args.kappa_steps or W.lanczos_steps
+    dev = torch.device("cuda:0")
+    A = bjp.DeviceCsr.from_host(W.A, dev)
+    b = torch.as_tensor(W.b, device=dev)
+    pcg_ws = bjp.PcgWorkspace(A)
+    kap_ws = bjp.KappaWorkspace(A, steps_k)
+    torch.cuda.synchronize()
+
+    def step(timer=None):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        ev[0].record()
+        M = bjp.precondition(A, block_size=W.block_size)
+        ev[1].record()
+        x, info = bjp.pcg_solve(A, M, b, tol=W.tol, workspace=pcg_ws, timer=timer)
+        ev[2].record()
+        kA = bjp.kappa_estimate(A, b, steps_k, None, workspace=kap_ws)
+        ev[3].record()
+        kM = bjp.kappa_estimate(A, b, steps_k, M, workspace=kap_ws)
+        ev[4].record()
+        return M, info, kA, kM, ev
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    cap = 4096
+    timers = [bjp.KernelTimer(bjp.KERNEL_APPLY, cap) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    t_wall = time.time()
+    start.record()
+    results = [step(timers[i]) for i in range(args.steps)]
+    end.record()
+    torch.cuda.synchronize()
+    wall_s = time.time() - t_wall
+    total_ms = start.elapsed_time(end)
+
+    setup_ms = [r[4][0].elapsed_time(r[4][1]) for r in results]
+    pcg_ms = [r[4][1].elapsed_time(r[4][2]) for r in results]
+    kapA_ms = [r[4][2].elapsed_time(r[4][3]) for r in results]
+    kapM_ms = [r[4][3].elapsed_time(r[4][4]) for r in results]
+    iters = [r[1].iterations for r in results]
+    M, info, kA, kM, _ = results[-1]
+    for r in results:
+        assert r[1].status == "OK" and r[1].rel_res_true <= W.tol, r[1]
+        assert r[2].status == "OK" and r[3].status == "OK"
+
+    value = sum(iters) / (sum(pcg_ms) / 1e3)
+    durs = []
+    for tmr, r in zip(timers, results):
+        d = tmr.durations_ms()[: r[1].iterations]
+        durs.extend(d)
+    apply_avg_ms = float(np.mean(durs))
+    off = M.offsets()
+    elem = 4 if M.precision == bjp.FP32_STORE else 8
+    ab = apply_bytes(W.A.n, off, elem)
+    achieved = ab / (apply_avg_ms * 1e-3) / 1e9
+    B_iter = ab + spmv_bytes(W.A.n, W.A.nnz)
+    iter_gbs = B_iter * sum(iters) / (sum(pcg_ms) / 1e3) / 1e9
+    traffic = read_traffic(f"apply_{args.workload}")
+
+    line = {
+        "metric": "PCG iters/s + achieved HBM GB/s at 1e-10 rel residual; κ(A)/κ(M⁻¹A)",
+        "value": round(value, 2),
+        "unit": "PCG iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(total_ms / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": W.A.n, "nnz": W.A.nnz,
+                   "block_size": W.block_size, "tol": W.tol, "lanczos_steps": steps_k,
+                   "parallelism": "single GPU"},
+        "pcg_iterations": iters[-1],
+        "pcg_ms": round(float(np.median(pcg_ms)), 3),
+        "us_per_iteration": round(1e3 * sum(pcg_ms) / sum(iters), 2),
+        "iteration_hbm_gbps": round(iter_gbs, 1),
+        "iteration_bytes": B_iter,
+        "setup_ms": round(float(np.median(setup_ms)), 3),
+        "kappa_A_ms": round(float(np.median(kapA_ms)), 3),
+        "kappa_MA_ms": round(float(np.median(kapM_ms)), 3),
+        "kappa_A": kA.kappa,
+        "kappa_MA": kM.kappa,
+        "rel_res_true": info.rel_res_true,
+        "roofline": {"bound": "hbm", "kernel": "k_apply (block inverse + x/r update)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "bytes_per_launch": ab, "avg_launch_us": round(apply_avg_ms * 1e3, 3),
+                     "launches_timed": len(durs)},
+        "wall_s": round(wall_s, 3),
+        "gen_s": round(gen_s, 2),
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+
+        Mo_t = time.time()
+        Mo = oracle.Precond.uniform(W.A, W.block_size)
+        setup_cpu = time.time() - Mo_t
+        t = time.time()
+        r = oracle.pcg(W.A, W.b, Mo, tol=W.tol, max_iter=args.cpu_iters, max_replacements=0)
+        dt = time.time() - t
+        line["cpu_baseline"] = {
+            "value": round(r.iterations / dt, 3), "unit": "PCG iterations/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{r.iterations} PCG iterations of the same {args.workload} system "
+                      f"(single-threaded FP64 C oracle; its setup took {setup_cpu:.1f} s, not included)"}
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -122,6 +122,24 @@ int bjp_precondition(const bjp_csr_t *A, const bjp_block_spec_t *spec, int preci
  * overlap.  Asynchronous. */
 int bjp_apply(const bjp_precond_t *M, const double *r, double *z, hipStream_t stream);
 
+/* Optional kernel timing.  When a solver is given one, every launch of the
+ * selected kernel inside its iteration loop is bracketed by a pair of
+ * events recorded on the solver's stream: events[2i] before, events[2i+1]
+ * after launch i, for the first `capacity` launches.  The events are
+ * created and destroyed by the caller (host array of 2*capacity handles). */
+typedef enum {
+    BJP_KERNEL_APPLY = 0,   /* the block-inverse application (x, r update + z = M^-1 r) */
+    BJP_KERNEL_SPMV = 1     /* the sparse product q = A p (with the fused direction) */
+} bjp_kernel_id;
+
+typedef struct {
+    int32_t kernel;         /* bjp_kernel_id */
+    int32_t capacity;       /* event pairs available */
+    int32_t recorded;       /* out: pairs recorded */
+    int32_t pad;
+    hipEvent_t *events;     /* host array [2*capacity] */
+} bjp_timing_t;
+
 /* Solver options.  Zero-initialised fields take the defaults noted. */
 typedef struct {
     double tol;               /* relative residual target (default 1e-10)          */
@@ -133,6 +151,7 @@ typedef struct {
     int32_t fuse_direction;   /* -1 = auto, 0 = separate p update, 1 = fused in SpMV */
     double *history;          /* device, optional, >= max_iter+1 entries: recursive
                                  relative residual after each iteration             */
+    bjp_timing_t *timing;     /* host, optional kernel timing (see bjp_timing_t)    */
 } bjp_pcg_opts_t;
 
 typedef struct {

@@ -40,11 +40,39 @@ class PrecondT(C.Structure):
                 ("offsets", C.c_void_p), ("tiles", C.c_void_p)]
 
 
+class TimingT(C.Structure):
+    _fields_ = [("kernel", C.c_int32), ("capacity", C.c_int32), ("recorded", C.c_int32),
+                ("pad", C.c_int32), ("events", C.c_void_p)]
+
+
 class PcgOptsT(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("x0_given", C.c_int32),
                 ("max_replacements", C.c_int32), ("check_every", C.c_int32),
                 ("spmv_lanes", C.c_int32), ("fuse_direction", C.c_int32),
-                ("history", C.c_void_p)]
+                ("history", C.c_void_p), ("timing", C.c_void_p)]
+
+
+KERNEL_APPLY, KERNEL_SPMV = 0, 1
+
+
+class KernelTimer:
+    """Event pairs that the solver records around one kernel class.
+
+    Uses torch.cuda.Event objects (HIP events); durations are read after the
+    solve with Event.elapsed_time."""
+
+    def __init__(self, kernel: int, capacity: int):
+        self.events = [torch.cuda.Event(enable_timing=True) for _ in range(2 * capacity)]
+        for e in self.events:
+            e.record()          # materialise the underlying HIP event
+        torch.cuda.synchronize()
+        self._handles = (C.c_void_p * (2 * capacity))(*[e.cuda_event for e in self.events])
+        self.struct = TimingT(kernel, capacity, 0, 0, C.cast(self._handles, C.c_void_p))
+
+    def durations_ms(self) -> list:
+        torch.cuda.synchronize()
+        n = self.struct.recorded
+        return [self.events[2 * i].elapsed_time(self.events[2 * i + 1]) for i in range(n)]
 
 
 class PcgInfoT(C.Structure):
@@ -239,7 +267,8 @@ class PcgWorkspace:
 def pcg_solve(A: DeviceCsr, M: Precond | None, b, tol: float = 1e-10, max_iter: int | None = None,
               x0=None, out: torch.Tensor | None = None, max_replacements: int = 3,
               check_every: int = 0, spmv_lanes: int = 0, fuse_direction: int = -1,
-              history: torch.Tensor | None = None, workspace: PcgWorkspace | None = None):
+              history: torch.Tensor | None = None, workspace: PcgWorkspace | None = None,
+              timer: KernelTimer | None = None):
     """bjp_pcg_solve.  Returns (x, PcgInfo); solver failures are reported in
     info.status, argument/workspace/runtime errors raise BjpError."""
     L = load()
@@ -255,7 +284,8 @@ def pcg_solve(A: DeviceCsr, M: Precond | None, b, tol: float = 1e-10, max_iter: 
     opts = PcgOptsT(tol, int(max_iter or 0), 1 if x0 is not None else 0,
                     -1 if max_replacements == 0 else int(max_replacements), int(check_every),
                     int(spmv_lanes), int(fuse_direction),
-                    history.data_ptr() if history is not None else None)
+                    history.data_ptr() if history is not None else None,
+                    C.cast(C.pointer(timer.struct), C.c_void_p) if timer is not None else None)
     info = PcgInfoT()
     st = L.bjp_pcg_solve(C.byref(A.struct()), C.byref(M.handle) if M is not None else None,
                          _ptr(b), _ptr(x), C.byref(opts), _ptr(ws.ws), ws.ws.numel(), C.byref(info),

@@ -22,6 +22,21 @@ HIPCC_FLAGS = [
 ]
 
 
+def source_digest() -> str:
+    """sha256 over the library sources and header (identifies a kernel build)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    files = [os.path.join(ROOT, "include", "bjp.h")]
+    csrc = os.path.join(PKG, "csrc")
+    files += [os.path.join(csrc, f) for f in sorted(os.listdir(csrc))]
+    for f in files:
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def hipcc() -> str:
     rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
     cand = os.path.join(rocm, "bin", "hipcc")

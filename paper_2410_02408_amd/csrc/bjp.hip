@@ -485,16 +485,29 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
         else hipLaunchKernelGGL((k_rows_update<APPLY_INIT>), dim3(La.grid), dim3(kWG), 0, stream, aa, n,
                                 La.chunk);
     };
+    bjp_timing_t *tm = o.timing;
+    if (tm) tm->recorded = 0;
+    auto mark = [&](int kernel, int which) {
+        if (!tm || tm->kernel != kernel || tm->recorded >= tm->capacity || !tm->events) return;
+        (void)hipEventRecord(tm->events[2 * tm->recorded + which], stream);
+        if (which == 1) tm->recorded++;
+    };
     auto iteration = [&]() {
         if (fuse) {
+            mark(BJP_KERNEL_SPMV, 0);
             launch_spmv<SPMV_DIR>(gs, Ls.grid, sa, stream);
+            mark(BJP_KERNEL_SPMV, 1);
         } else {
             hipLaunchKernelGGL(k_direction, dim3(fill_grid), dim3(kWG), 0, stream, st, z, p0, p1, n);
+            mark(BJP_KERNEL_SPMV, 0);
             launch_spmv<SPMV_SIGMA>(gs, Ls.grid, sa, stream);
+            mark(BJP_KERNEL_SPMV, 1);
         }
+        mark(BJP_KERNEL_APPLY, 0);
         if (M) launch_apply<APPLY_UPDATE>(M, La.grid, aa, stream);
         else hipLaunchKernelGGL((k_rows_update<APPLY_UPDATE>), dim3(La.grid), dim3(kWG), 0, stream, aa,
                                 n, La.chunk);
+        mark(BJP_KERNEL_APPLY, 1);
     };
     auto read_state = [&](PcgState &h) -> int {
         HIP_TRY(hipGetLastError());
