@@ -95,11 +95,13 @@ typedef enum {
  * symmetric block inverses diagonal by diagonal (see the kernels). */
 typedef struct {
     int32_t n;
+    int32_t block_size;       /* uniform block size, or 0 for an explicit partition */
     int32_t num_blocks;
     int32_t precision;        /* bjp_precision */
     int32_t group;            /* lanes per block, power of two <= 64 */
     int32_t num_packets;
     int32_t packet_elems;     /* scalars per packet */
+    int32_t pad;
     const int32_t *offsets;   /* device [num_blocks+1] */
     const void *tiles;        /* device, num_packets * packet_elems scalars */
 } bjp_precond_t;

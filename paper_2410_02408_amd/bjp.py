@@ -35,8 +35,9 @@ class BlockSpecT(C.Structure):
 
 
 class PrecondT(C.Structure):
-    _fields_ = [("n", C.c_int32), ("num_blocks", C.c_int32), ("precision", C.c_int32),
-                ("group", C.c_int32), ("num_packets", C.c_int32), ("packet_elems", C.c_int32),
+    _fields_ = [("n", C.c_int32), ("block_size", C.c_int32), ("num_blocks", C.c_int32),
+                ("precision", C.c_int32), ("group", C.c_int32), ("num_packets", C.c_int32),
+                ("packet_elems", C.c_int32), ("pad", C.c_int32),
                 ("offsets", C.c_void_p), ("tiles", C.c_void_p)]
 
 

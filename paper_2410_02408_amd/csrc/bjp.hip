@@ -13,6 +13,7 @@
 #include "bjp.h"
 #include "blocks.hpp"
 #include "common.hpp"
+#include "finish.hpp"
 #include "lanczos.hpp"
 #include "spmv.hpp"
 
@@ -104,7 +105,6 @@ __global__ void k_pcg_state_init(PcgState *st, double tol, int max_iter) {
     st->max_iter = max_iter;
     st->zero_rhs = 0;
     st->pad = 0;
-    for (int i = 0; i < 4; ++i) st->counter[i] = 0u;
 }
 
 __global__ void k_pcg_restart(PcgState *st) {
@@ -124,27 +124,27 @@ __global__ void k_lanczos_state_init(LanczosState *ls, int steps) {
     ls->steps_done = 0;
     ls->steps = steps;
     ls->pad = 0;
-    for (int i = 0; i < 4; ++i) ls->counter[i] = 0u;
 }
 
-// Lanczos start: beta_0 = sqrt(r^T z) for z = M^-1 r (z == r when M = I).
+// Lanczos start: partial r^T z for z = M^-1 r (z == r when M = I); the
+// finish kernel turns it into 1 / beta_0.
 __global__ __launch_bounds__(kWG) void k_lanczos_start(LanczosState *ls, const double *r,
                                                        const double *z, int n, int chunk,
                                                        double *partials) {
+    if (ls->done) return;
     const int c = xcd_chunk(blockIdx.x, gridDim.x);
     const int r0 = c * chunk, r1 = min(r0 + chunk, n);
     double s = 0.0;
     for (int i = r0 + threadIdx.x; i < r1; i += kWG) s += r[i] * z[i];
-    double v[1] = {s}, out[1];
-    if (grid_sum<1>(v, partials, &ls->counter[0], out) && threadIdx.x == 0) {
-        const double bb = out[0];
-        if (!(bb > 0.0)) {
-            ls->status = isfinite(bb) ? BJP_EBREAKDOWN : BJP_ENONFINITE;
-            ls->done = 1;
-        } else {
-            ls->invb = 1.0 / sqrt(bb);
-        }
-    }
+    const double v[1] = {s};
+    block_partial<1>(v, partials);
+}
+
+template <int OP>
+void finish(const FinishArgs &f, int nparts, hipStream_t s) {
+    FinishArgs g = f;
+    g.nparts = nparts;
+    hipLaunchKernelGGL((k_finish<OP>), dim3(1), dim3(kWG), 0, s, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -258,7 +258,7 @@ struct RowLaunch {
 };
 
 RowLaunch spmv_shape(int n, int gs) {
-    const int u = gs <= 16 ? 4 : 2;
+    const int u = spmv_rows_per_group(gs);
     const int rows_per_step = (kWG / gs) * u;
     const int grid = round8(std::min(ceil_div(n, rows_per_step), kMaxRedWG));
     return {grid, ceil_div(n, grid)};
@@ -278,6 +278,19 @@ RowLaunch gram_shape(int n) {
     const int per = kWG * kGramRows;
     const int grid = round8(ceil_div(n, per));
     return {grid, per};
+}
+
+// A handle must describe a partition whose packets the kernels can address.
+bool precond_ok(const bjp_precond_t *M, int n) {
+    if (!M || M->n != n || !M->tiles || !M->offsets) return false;
+    const int G = M->group;
+    if (G < 1 || G > 64 || (G & (G - 1))) return false;
+    if (M->num_blocks < (n > 0 ? 1 : 0) || M->num_packets != ceil_div(M->num_blocks, 64 / G)) return false;
+    if (M->packet_elems != packet_elems(G)) return false;
+    if (M->precision != BJP_FP64 && M->precision != BJP_FP32_STORE) return false;
+    if (M->block_size < 0 || M->block_size > G) return false;
+    if (M->block_size > 0 && M->num_blocks != ceil_div(n, M->block_size)) return false;
+    return true;
 }
 
 int auto_lanes(const bjp_csr_t *A) {
@@ -342,6 +355,7 @@ int bjp_precondition(const bjp_csr_t *A, const bjp_block_spec_t *spec, int preci
     int32_t *flags = cv.take<int32_t>(16);
 
     M_out->n = A->n;
+    M_out->block_size = spec->block_size > 0 ? spec->block_size : 0;
     M_out->num_blocks = P.nblocks;
     M_out->precision = precision;
     M_out->group = P.G;
@@ -371,12 +385,14 @@ int bjp_precondition(const bjp_csr_t *A, const bjp_block_spec_t *spec, int preci
 }
 
 int bjp_apply(const bjp_precond_t *M, const double *r, double *z, hipStream_t stream) {
-    if (!M || M->n < 0 || (M->n > 0 && (!r || !z || !M->tiles || !M->offsets))) return BJP_EINVAL;
-    if (M->group < 1 || M->group > 64 || (M->group & (M->group - 1))) return BJP_EINVAL;
+    if (!M || M->n < 0) return BJP_EINVAL;
     if (M->n == 0) return BJP_OK;
+    if (!r || !z || !precond_ok(M, M->n)) return BJP_EINVAL;
     ApplyArgs a{};
     a.nblocks = M->num_blocks;
     a.num_packets = M->num_packets;
+    a.n = M->n;
+    a.uniform_nb = M->block_size;
     a.off = M->offsets;
     a.tiles = M->tiles;
     a.rin = r;
@@ -393,7 +409,7 @@ int bjp_pcg_workspace(const bjp_csr_t *A, size_t *bytes) {
     *bytes = 0;
     if (check_csr_host(A) != BJP_OK) return BJP_EINVAL;
     const size_t vec = al256(sizeof(double) * (size_t)std::max(A->n, 1));
-    *bytes = 5 * vec + al256(sizeof(double) * 2 * kMaxRedWG) + al256(sizeof(PcgState)) + al256(64);
+    *bytes = 5 * vec + al256(sizeof(double) * 2 * kMaxRedWG) + al256(sizeof(PcgState)) + 2 * al256(64);
     return BJP_OK;
 }
 
@@ -409,7 +425,7 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
     if (check_csr_host(A) != BJP_OK) return fail(BJP_EINVAL);
     const int n = A->n;
     if (n > 0 && (!b || !x)) return fail(BJP_EINVAL);
-    if (M && (M->n != n || !M->tiles || !M->offsets)) return fail(BJP_EINVAL);
+    if (M && n > 0 && !precond_ok(M, n)) return fail(BJP_EINVAL);
     bjp_pcg_opts_t o{};
     if (opts) o = *opts;
     if (!(o.tol > 0.0)) o.tol = 1e-10;
@@ -428,6 +444,7 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
     double *partials = cv.take<double>(2 * kMaxRedWG);
     PcgState *st = cv.take<PcgState>(1);
     int32_t *flags = cv.take<int32_t>(16);
+    double *zeros = cv.take<double>(8);
     if (!M) z = r;  // plain CG: the "preconditioned" residual is r itself
 
     int s = run_validate(A, flags, stream);
@@ -440,6 +457,7 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
     const int fill_grid = std::min(ceil_div(n, kWG), 4096);
 
     hipLaunchKernelGGL(k_pcg_state_init, dim3(1), dim3(64), 0, stream, st, o.tol, o.max_iter);
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, stream, zeros, 8, 0.0);
     hipLaunchKernelGGL(k_fill, dim3(fill_grid), dim3(kWG), 0, stream, p0, n, 0.0);
     hipLaunchKernelGGL(k_fill, dim3(fill_grid), dim3(kWG), 0, stream, p1, n, 0.0);
     if (!o.x0_given) hipLaunchKernelGGL(k_fill, dim3(fill_grid), dim3(kWG), 0, stream, x, n, 0.0);
@@ -448,8 +466,8 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
     sa.n = n;
     sa.chunk = Ls.chunk;
     sa.rp = A->row_ptr;
-    sa.ci = A->col_idx;
-    sa.val = A->val;
+    sa.ci = A->nnz > 0 ? A->col_idx : reinterpret_cast<const int32_t *>(zeros);
+    sa.val = A->nnz > 0 ? A->val : zeros;
     sa.st = st;
     sa.z = z;
     sa.p0 = p0;
@@ -458,13 +476,19 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
     sa.b = b;
     sa.x = x;
     sa.r = r;
-    sa.hist = o.history;
     sa.partials = partials;
 
+    FinishArgs fa{};
+    fa.st = st;
+    fa.partials = partials;
+    fa.hist = o.history;
+
     ApplyArgs aa{};
+    aa.n = n;
     if (M) {
         aa.nblocks = M->num_blocks;
         aa.num_packets = M->num_packets;
+        aa.uniform_nb = M->block_size;
         aa.off = M->offsets;
         aa.tiles = M->tiles;
     }
@@ -477,13 +501,13 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
     aa.q = q;
     aa.p0 = p0;
     aa.p1 = p1;
-    aa.hist = o.history;
     aa.partials = partials;
 
     auto start_direction = [&]() {
         if (M) launch_apply<APPLY_INIT>(M, La.grid, aa, stream);
         else hipLaunchKernelGGL((k_rows_update<APPLY_INIT>), dim3(La.grid), dim3(kWG), 0, stream, aa, n,
                                 La.chunk);
+        finish<FIN_PCG_START>(fa, La.grid, stream);
     };
     bjp_timing_t *tm = o.timing;
     if (tm) tm->recorded = 0;
@@ -503,11 +527,14 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
             launch_spmv<SPMV_SIGMA>(gs, Ls.grid, sa, stream);
             mark(BJP_KERNEL_SPMV, 1);
         }
+        finish<FIN_SIGMA>(fa, Ls.grid, stream);
         mark(BJP_KERNEL_APPLY, 0);
         if (M) launch_apply<APPLY_UPDATE>(M, La.grid, aa, stream);
         else hipLaunchKernelGGL((k_rows_update<APPLY_UPDATE>), dim3(La.grid), dim3(kWG), 0, stream, aa,
                                 n, La.chunk);
         mark(BJP_KERNEL_APPLY, 1);
+        if (M) finish<FIN_PCG_UPDATE>(fa, La.grid, stream);
+        else finish<FIN_PCG_UPDATE_I>(fa, La.grid, stream);
     };
     auto read_state = [&](PcgState &h) -> int {
         HIP_TRY(hipGetLastError());
@@ -518,6 +545,7 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
 
     sa.resid_phase = 0;
     launch_spmv<SPMV_RESID>(gs, Ls.grid, sa, stream);
+    finish<FIN_RESID_START>(fa, Ls.grid, stream);
     start_direction();
 
     PcgState h{};
@@ -547,6 +575,7 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
         // converged on the recursive residual: confirm with the true one
         sa.resid_phase = 1;
         launch_spmv<SPMV_RESID>(gs, Ls.grid, sa, stream);
+        finish<FIN_RESID_TRUE>(fa, Ls.grid, stream);
         if ((s = read_state(h)) != BJP_OK) return fail(s);
         if (h.relres_true <= o.tol) break;
         if (replacements >= o.max_replacements) {
@@ -567,6 +596,7 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
     } else if (status != BJP_OK) {
         sa.resid_phase = 1;
         launch_spmv<SPMV_RESID>(gs, Ls.grid, sa, stream);
+        finish<FIN_RESID_TRUE>(fa, Ls.grid, stream);
         if ((s = read_state(h)) != BJP_OK) return fail(s);
     }
     info->status = status;
@@ -592,7 +622,7 @@ int bjp_kappa_workspace(const bjp_csr_t *A, int steps, size_t *bytes) {
              + al256(sizeof(double) * (size_t)Lg.grid * (steps + 1))  // Gram partials
              + 2 * al256(sizeof(double) * steps)              // alpha, beta
              + al256(sizeof(double) * 2 * redwg)              // grid_sum partials
-             + al256(sizeof(LanczosState)) + al256(64);
+             + al256(sizeof(LanczosState)) + 2 * al256(64);
     return BJP_OK;
 }
 
@@ -608,7 +638,7 @@ int bjp_kappa_estimate(const bjp_csr_t *A, const bjp_precond_t *M, const double 
     if (check_csr_host(A) != BJP_OK || steps <= 0) return fail(BJP_EINVAL);
     const int n = A->n;
     if (n == 0 || !v0) return fail(BJP_EINVAL);
-    if (M && (M->n != n || !M->tiles || !M->offsets)) return fail(BJP_EINVAL);
+    if (M && n > 0 && !precond_ok(M, n)) return fail(BJP_EINVAL);
     size_t need = 0;
     bjp_kappa_workspace(A, steps, &need);
     if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255)) return fail(BJP_EWORKSPACE);
@@ -626,6 +656,7 @@ int bjp_kappa_estimate(const bjp_csr_t *A, const bjp_precond_t *M, const double 
     double *partials = cv.take<double>(2 * redwg);
     LanczosState *ls = cv.take<LanczosState>(1);
     int32_t *flags = cv.take<int32_t>(16);
+    double *zeros = cv.take<double>(8);
     if (!M) {
         V = U;     // M = I: u_j == v_j
         zt = rt;
@@ -638,12 +669,15 @@ int bjp_kappa_estimate(const bjp_csr_t *A, const bjp_precond_t *M, const double 
     const RowLaunch Ls = spmv_shape(n, gs);
     const RowLaunch Lr = rows_shape(n);
     hipLaunchKernelGGL(k_lanczos_state_init, dim3(1), dim3(64), 0, stream, ls, steps);
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, stream, zeros, 8, 0.0);
     HIP_TRY(hipMemcpyAsync(rt, v0, sizeof(double) * n, hipMemcpyDeviceToDevice, stream));
 
     ApplyArgs aa{};
+    aa.n = n;
     if (M) {
         aa.nblocks = M->num_blocks;
         aa.num_packets = M->num_packets;
+        aa.uniform_nb = M->block_size;
         aa.off = M->offsets;
         aa.tiles = M->tiles;
     }
@@ -652,18 +686,23 @@ int bjp_kappa_estimate(const bjp_csr_t *A, const bjp_precond_t *M, const double 
     aa.rin = rt;
     aa.zout = zt;
     aa.ls = ls;
-    aa.beta_out = be;
     aa.partials = partials;
+    FinishArgs fl{};
+    fl.ls = ls;
+    fl.partials = partials;
+    fl.alpha_out = al;
+    fl.beta_out = be;
     if (M) launch_apply<APPLY_PLAIN>(M, La.grid, aa, stream);
     hipLaunchKernelGGL(k_lanczos_start, dim3(Lr.grid), dim3(kWG), 0, stream, ls, rt, zt, n, Lr.chunk,
                        partials);
+    finish<FIN_LZ_START>(fl, Lr.grid, stream);
 
     SpmvArgs sa{};
     sa.n = n;
     sa.chunk = Ls.chunk;
     sa.rp = A->row_ptr;
-    sa.ci = A->col_idx;
-    sa.val = A->val;
+    sa.ci = A->nnz > 0 ? A->col_idx : reinterpret_cast<const int32_t *>(zeros);
+    sa.val = A->nnz > 0 ? A->val : zeros;
     sa.ls = ls;
     sa.zt = zt;
     sa.rt = rt;
@@ -671,7 +710,6 @@ int bjp_kappa_estimate(const bjp_csr_t *A, const bjp_precond_t *M, const double 
     sa.U = U;
     sa.ld = ld;
     sa.w = w;
-    sa.alpha_out = al;
     sa.has_m = M ? 1 : 0;
     sa.partials = partials;
 
@@ -688,18 +726,23 @@ int bjp_kappa_estimate(const bjp_csr_t *A, const bjp_precond_t *M, const double 
     ga.cpart = cpart;
     ga.ldc = steps + 1;
     ga.has_m = M ? 1 : 0;
-    ga.beta_out = be;
     ga.partials = partials;
 
     LanczosState h{};
     for (int j = 0; j < steps; ++j) {
         launch_spmv<SPMV_LANCZOS>(gs, Ls.grid, sa, stream);
+        finish<FIN_LZ_ALPHA>(fl, Ls.grid, stream);
         hipLaunchKernelGGL((k_gram<GRAM_FIRST>), dim3(Lg.grid), dim3(kWG), 0, stream, ga);
         hipLaunchKernelGGL(k_gram_reduce, dim3(j + 1), dim3(kWG), 0, stream, ls, cpart, steps + 1, Lg.grid, c);
         hipLaunchKernelGGL((k_gram<GRAM_SECOND>), dim3(Lg.grid), dim3(kWG), 0, stream, ga);
         hipLaunchKernelGGL(k_gram_reduce, dim3(j + 1), dim3(kWG), 0, stream, ls, cpart, steps + 1, Lg.grid, c);
         hipLaunchKernelGGL((k_gram<GRAM_FINAL>), dim3(Lg.grid), dim3(kWG), 0, stream, ga);
-        if (M) launch_apply<APPLY_LANCZOS>(M, La.grid, aa, stream);
+        if (M) {
+            launch_apply<APPLY_LANCZOS>(M, La.grid, aa, stream);
+            finish<FIN_LZ_BETA>(fl, La.grid, stream);
+        } else {
+            finish<FIN_LZ_BETA>(fl, Lg.grid, stream);
+        }
         HIP_TRY(hipGetLastError());
         if ((j & 31) == 31 && j + 1 < steps) {
             HIP_TRY(hipMemcpyAsync(&h, ls, sizeof(h), hipMemcpyDeviceToHost, stream));

@@ -134,6 +134,8 @@ enum ApplyMode { APPLY_PLAIN = 0, APPLY_INIT = 1, APPLY_UPDATE = 2, APPLY_LANCZO
 
 struct ApplyArgs {
     int nblocks, num_packets, chunk;
+    int n;                  // rows of the system
+    int uniform_nb;         // > 0: block t = rows [t*nb, min((t+1)*nb, n)), offsets unused
     const int32_t *off;
     const void *tiles;
     const double *rin;      // PLAIN / INIT / LANCZOS: residual to precondition
@@ -142,66 +144,9 @@ struct ApplyArgs {
     double *x, *r;          // UPDATE: x += alpha p, r -= alpha q
     const double *q;
     double *p0, *p1;        // UPDATE: p_new = p[(it+1)&1]
-    double *hist;           // optional residual history
     LanczosState *ls;       // LANCZOS
-    double *beta_out;
-    double *partials;
+    double *partials;       // per-workgroup r^T z, r^T r
 };
-
-// Last-workgroup decisions shared by the preconditioned and plain variants.
-__device__ __forceinline__ void pcg_after_init(PcgState *st, double rz) {
-    if (!(rz > 0.0)) {
-        st->status = isfinite(rz) ? BJP_EBREAKDOWN : BJP_ENONFINITE;
-        st->done = 1;
-    } else {
-        st->rho = rz;
-        st->beta = 0.0;
-    }
-}
-
-__device__ __forceinline__ void pcg_after_update(PcgState *st, double rz, double rr, double *hist) {
-    const int it = st->it + 1;
-    st->it = it;
-    const double relres = sqrt(rr) / sqrt(st->bnorm2);
-    st->relres = relres;
-    if (hist) hist[it] = relres;
-    if (!isfinite(rr)) {
-        st->status = BJP_ENONFINITE;
-        st->done = 1;
-    } else if (relres <= st->tol) {
-        st->done = 1;
-    } else if (!(rz > 0.0)) {
-        st->status = isfinite(rz) ? BJP_EBREAKDOWN : BJP_ENONFINITE;
-        st->done = 1;
-    } else {
-        st->beta = rz / st->rho;
-        st->rho = rz;
-        if (it >= st->max_iter) {
-            st->status = BJP_ENOCONV;
-            st->done = 1;
-        }
-    }
-}
-
-__device__ __forceinline__ void lanczos_after_beta(LanczosState *ls, double bb, double *beta_out) {
-    const int j = ls->j;
-    ls->steps_done = j + 1;
-    if (!isfinite(bb)) {
-        ls->status = BJP_ENONFINITE;
-        ls->done = 1;
-        return;
-    }
-    const double b = sqrt(bb > 0.0 ? bb : 0.0);
-    if (j + 1 == ls->steps || b <= 1e-12 * ls->scale) {
-        ls->done = 1;
-        return;
-    }
-    if (b > ls->scale) ls->scale = b;
-    if (beta_out) beta_out[j] = b;
-    ls->invb = 1.0 / b;
-    ls->beta_prev = b;
-    ls->j = j + 1;
-}
 
 template <int G, typename TS, int MODE>
 __global__ __launch_bounds__(kWG) void k_apply(ApplyArgs a) {
@@ -219,41 +164,61 @@ __global__ __launch_bounds__(kWG) void k_apply(ApplyArgs a) {
     const int pk1 = min(pk0 + a.chunk, a.num_packets);
 
     double alpha = 0.0;
-    const double *pn = nullptr;
+    const double *__restrict__ pn = nullptr;
     if (MODE == APPLY_UPDATE) {
         alpha = a.st->alpha;
         pn = ((a.st->it + 1) & 1) ? a.p1 : a.p0;
     }
+    const TS *__restrict__ tiles = static_cast<const TS *>(a.tiles);
+    const int32_t *__restrict__ off = a.off;
+    double *__restrict__ xv_ = a.x;
+    double *__restrict__ rv_ = a.r;
+    const double *__restrict__ qv_ = a.q;
+    const double *__restrict__ rin = a.rin;
+    double *__restrict__ zout = a.zout;
     double d0 = 0.0, d1 = 0.0;
     for (int pk = pk0 + wave; pk < pk1; pk += kWaves) {
+        // The packet's diagonals are issued first: they are the bulk of the
+        // bytes and do not depend on anything else in the iteration.
+        const TS *D = tiles + (size_t)pk * E;
+        TS dv[K + 1];
+        dv[0] = D[lane];
+#pragma unroll
+        for (int k = 1; k <= K; ++k) dv[k] = k < K ? D[k * 64 + lane] : D[K * 64 + g * K + (i & (K - 1))];
+
         const int t = pk * P + g;
         int s = 0, n = 0;
-        if (t < a.nblocks) {
-            s = a.off[t];
-            n = a.off[t + 1] - s;
+        if (a.uniform_nb > 0) {
+            s = t * a.uniform_nb;
+            n = max(0, min(a.uniform_nb, a.n - s));
+        } else {
+            const int tc = min(t, a.nblocks - 1);
+            const int s0 = off[tc], e0 = off[tc + 1];
+            s = t < a.nblocks ? s0 : 0;
+            n = t < a.nblocks ? e0 - s0 : 0;
         }
         const bool act = i < n;
         const int row = s + i;
-        double rv = 0.0;
-        if (act) {
-            if (MODE == APPLY_UPDATE) {
-                const double xv = a.x[row], pv = pn[row], qv = a.q[row];
-                rv = a.r[row];
-                a.x[row] = fma(alpha, pv, xv);
-                rv = fma(-alpha, qv, rv);
-                a.r[row] = rv;
-            } else {
-                rv = a.rin[row];
+        const int rc = min(row, a.n - 1);      // in-bounds index for masked lanes
+        double rv;
+        if (MODE == APPLY_UPDATE) {
+            const double xo = xv_[rc], pv = pn[rc], qv = qv_[rc], ro = rv_[rc];
+            rv = act ? fma(-alpha, qv, ro) : 0.0;
+            if (act) {
+                xv_[row] = fma(alpha, pv, xo);
+                rv_[row] = rv;
             }
+        } else {
+            const double ro = rin[rc];
+            rv = act ? ro : 0.0;
         }
-        const TS *D = static_cast<const TS *>(a.tiles) + (size_t)pk * E;
         const TS rs = (TS)rv;
-        TS zv = D[lane] * rs;
+        TS zv = dv[0] * rs;
         const int ia = act ? i : 0;
         const int nn = n > 0 ? n : 1;
 #pragma unroll
         for (int k = 1; k <= K; ++k) {
-            const TS v = k < K ? D[k * 64 + lane] : D[K * 64 + g * K + (i & (K - 1))];
+            const TS v = dv[k];
             int j1 = ia + k;
             if (j1 >= nn) j1 -= nn;
             int j2 = ia - k;
@@ -266,23 +231,14 @@ __global__ __launch_bounds__(kWG) void k_apply(ApplyArgs a) {
         }
         if (act) {
             const double z = (double)zv;
-            a.zout[row] = z;
+            zout[row] = z;
             d0 += rv * z;
             d1 += rv * rv;
         }
     }
     if (MODE == APPLY_PLAIN) return;
-    double v[2] = {d0, d1}, out[2];
-    unsigned int *counter = (MODE == APPLY_LANCZOS) ? &a.ls->counter[0] : &a.st->counter[0];
-    if (grid_sum<2>(v, a.partials, counter, out) && threadIdx.x == 0) {
-        if (MODE == APPLY_INIT) {
-            pcg_after_init(a.st, out[0]);
-        } else if (MODE == APPLY_UPDATE) {
-            pcg_after_update(a.st, out[0], out[1], a.hist);
-        } else {
-            lanczos_after_beta(a.ls, out[0], a.beta_out);
-        }
-    }
+    const double v[2] = {d0, d1};
+    block_partial<2>(v, a.partials);
 }
 
 // Preconditioner-free (M = I) counterpart of k_apply for PCG: z is r itself.
@@ -307,11 +263,8 @@ __global__ __launch_bounds__(kWG) void k_rows_update(ApplyArgs a, int n, int chu
         }
         d1 += rv * rv;
     }
-    double v[1] = {d1}, out[1];
-    if (grid_sum<1>(v, a.partials, &a.st->counter[0], out) && threadIdx.x == 0) {
-        if (MODE == APPLY_INIT) pcg_after_init(a.st, out[0]);
-        else pcg_after_update(a.st, out[0], out[0], a.hist);
-    }
+    const double v[1] = {d1};
+    block_partial<1>(v, a.partials);
 }
 
 }  // namespace bjp

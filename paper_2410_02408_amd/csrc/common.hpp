@@ -1,10 +1,10 @@
 // Shared device utilities for the block-Jacobi PCG library (gfx950, wave64).
 //
 // Reductions are deterministic: every workgroup reduces its values in a fixed
-// tree, writes one partial per quantity, and the last workgroup to arrive
-// (integer arrival counter, no floating-point atomics) sums all partials in a
-// fixed order.  The result therefore does not depend on scheduling, and two
-// runs on the same input are bitwise identical.
+// tree and writes one partial per quantity; a one-workgroup finish kernel then
+// sums the partials in a fixed order (no floating-point atomics).  The result
+// does not depend on scheduling, and two runs on the same input are bitwise
+// identical.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -33,26 +33,16 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-__device__ __forceinline__ void store_agent(double *p, double v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double load_agent(const double *p) {
-    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Grid-wide deterministic sum of NQ per-thread values.
-//   partials: [NQ][gridDim.x] doubles, counter: one uint32 that is zero on
-//   entry and is reset to zero by the last workgroup.
-// Must be called by every thread of every workgroup of the launch.  Returns
-// true in (every thread of) the last workgroup to arrive, where out[] holds
-// the totals; other workgroups return false and out[] is unspecified.
+// Per-workgroup partial sums of NQ per-thread values: a fixed-order tree
+// inside the workgroup, then thread 0 stores partials[q * gridDim.x + block].
+// The totals are formed by a one-workgroup finish kernel launched next on the
+// same stream (k_finish), so no workgroup needs a device-scope release fence:
+// on gfx950 such a fence writes back the XCD's L2, and thousands of them per
+// launch cost more than the launch itself.  Must be called by every thread.
 template <int NQ>
-__device__ __forceinline__ bool grid_sum(const double (&v)[NQ], double *partials,
-                                         unsigned int *counter, double (&out)[NQ]) {
+__device__ __forceinline__ void block_partial(const double (&v)[NQ], double *partials) {
     __shared__ double red[NQ][kWaves];
-    __shared__ int is_last;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int G = gridDim.x;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         double s = wave_sum(v[q]);
@@ -64,26 +54,23 @@ __device__ __forceinline__ bool grid_sum(const double (&v)[NQ], double *partials
         for (int q = 0; q < NQ; ++q) {
             double s = 0.0;
             for (int w = 0; w < kWaves; ++w) s += red[q][w];
-            store_agent(&partials[q * G + blockIdx.x], s);
+            partials[q * gridDim.x + blockIdx.x] = s;
         }
-        __threadfence();
-        unsigned int prev = atomicAdd(counter, 1u);
-        is_last = (prev == (unsigned int)(G - 1));
     }
-    __syncthreads();
-    if (!is_last) return false;
-    __threadfence();
-    double acc[NQ];
+}
+
+// Sum of partials[q * nparts + b] over b, in a fixed order, for a
+// one-workgroup launch; every thread receives the totals.
+template <int NQ>
+__device__ __forceinline__ void sum_partials(const double *partials, int nparts, double (&out)[NQ]) {
+    __shared__ double red[NQ][kWaves];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        acc[q] = 0.0;
-        for (int b = tid; b < G; b += kWG) acc[q] += load_agent(&partials[q * G + b]);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        double s = wave_sum(acc[q]);
-        if (lane == 0) red[q][wave] = s;
+        double acc = 0.0;
+        for (int b = tid; b < nparts; b += kWG) acc += partials[q * nparts + b];
+        acc = wave_sum(acc);
+        if (lane == 0) red[q][wave] = acc;
     }
     __syncthreads();
 #pragma unroll
@@ -92,8 +79,6 @@ __device__ __forceinline__ bool grid_sum(const double (&v)[NQ], double *partials
         for (int w = 0; w < kWaves; ++w) s += red[q][w];
         out[q] = s;
     }
-    if (tid == 0) atomicExch(counter, 0u);
-    return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -114,7 +99,6 @@ struct PcgState {
     int32_t max_iter;
     int32_t zero_rhs;  // b == 0
     int32_t pad;
-    unsigned int counter[4];
 };
 
 struct LanczosState {
@@ -129,7 +113,6 @@ struct LanczosState {
     int32_t steps_done;
     int32_t steps;
     int32_t pad;
-    unsigned int counter[4];
 };
 
 }  // namespace bjp

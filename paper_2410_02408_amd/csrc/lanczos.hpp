@@ -36,8 +36,7 @@ struct GramArgs {
     double *cpart;           // FIRST / SECOND: partial coefficients [grid][ldc]
     int ldc;
     int has_m;
-    double *beta_out;        // FINAL with M = I
-    double *partials;        // FINAL with M = I: grid_sum scratch
+    double *partials;        // FINAL with M = I: per-workgroup r~^T r~
 };
 
 template <int PASS>
@@ -105,9 +104,8 @@ __global__ __launch_bounds__(kWG) void k_gram(GramArgs a) {
         double s = 0.0;
 #pragma unroll
         for (int q = 0; q < kGramRows; ++q) s += rv[q] * rv[q];
-        double v[1] = {s}, out[1];
-        if (grid_sum<1>(v, a.partials, &ls->counter[0], out) && tid == 0)
-            lanczos_after_beta(ls, out[0], a.beta_out);
+        const double v[1] = {s};
+        block_partial<1>(v, a.partials);
     }
 }
 

@@ -23,6 +23,12 @@ namespace bjp {
 
 enum SpmvMode { SPMV_DIR = 0, SPMV_SIGMA = 1, SPMV_RESID = 2, SPMV_LANCZOS = 3 };
 
+#ifndef BJP_SPMV_ROWS
+#define BJP_SPMV_ROWS 4
+#endif
+// Rows each lane group keeps in flight per step.
+__host__ __device__ constexpr int spmv_rows_per_group(int gs) { return gs <= 16 ? BJP_SPMV_ROWS : 2; }
+
 struct SpmvArgs {
     int n, chunk;
     const int32_t *rp, *ci;
@@ -34,16 +40,14 @@ struct SpmvArgs {
     const double *b;        // RESID
     const double *x;        // RESID
     double *r;              // RESID: r = b - A x
-    int resid_phase;        // RESID: 0 = start of a solve, 1 = final true residual
-    double *hist;
+    int resid_phase;        // RESID: 0 = start of a solve, 1 = true residual (runs when done)
     LanczosState *ls;       // LANCZOS
     const double *zt, *rt;  // LANCZOS: vectors to normalise (zt == rt when M = I)
     double *V, *U;          // LANCZOS: bases, vector l at l*ld (U unused when M = I)
     size_t ld;
     double *w;              // LANCZOS: w = A v_j
-    double *alpha_out;      // LANCZOS
     int has_m;
-    double *partials;
+    double *partials;       // per-workgroup dots (see the modes)
 };
 
 // The one place the updated direction is formed, so that the value gathered
@@ -60,8 +64,10 @@ __global__ __launch_bounds__(kWG) void k_spmv(SpmvArgs a) {
         if (a.st->done) return;
     }
     // U rows per lane group are processed together so that several
-    // row_ptr -> col -> gather chains are in flight per lane.
-    constexpr int U = GS <= 16 ? 4 : 2;
+    // row_ptr -> col -> gather chains are in flight per lane.  The CSR
+    // arrays must hold at least one entry (callers pass a zero entry for an
+    // empty matrix).
+    constexpr int U = spmv_rows_per_group(GS);
     constexpr int RWG = kWG / GS;
     const int tid = threadIdx.x, sub = tid & (GS - 1), grp = tid / GS;
     const int c = xcd_chunk(blockIdx.x, gridDim.x);
@@ -89,36 +95,43 @@ __global__ __launch_bounds__(kWG) void k_spmv(SpmvArgs a) {
         return src[col];
     };
 
+    // All loads of a step are unconditional (out-of-range rows and lanes use
+    // clamped, in-bounds indices and are masked afterwards), so the compiler
+    // issues them back to back instead of one exec-masked block at a time.
+    const int32_t *__restrict__ rp = a.rp;
+    const int32_t *__restrict__ ci = a.ci;
+    const double *__restrict__ val = a.val;
     double d0 = 0.0, d1 = 0.0;
     for (int base = r0; base < r1; base += RWG * U) {
         int kb[U], ke[U], row[U];
+        double own[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             row[u] = base + u * RWG + grp;
-            kb[u] = 0;
-            ke[u] = 0;
-            if (row[u] < r1) {
-                kb[u] = a.rp[row[u]];
-                ke[u] = a.rp[row[u] + 1];
-            }
+            const int rc = min(row[u], r1 - 1);
+            const int b0 = rp[rc], e0 = rp[rc + 1];
+            const bool ok = row[u] < r1;
+            kb[u] = ok ? b0 : 0;
+            ke[u] = ok ? e0 : 0;
+            if (MODE == SPMV_DIR) own[u] = dir_value(beta, pold, a.z, rc);
+            else if (MODE == SPMV_SIGMA) own[u] = pnew[rc];
+            else if (MODE == SPMV_RESID) own[u] = a.b[rc];
+            else own[u] = a.zt[rc] * invb;
         }
         int col[U];
         double vv[U], acc[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            col[u] = 0;
-            vv[u] = 0.0;
             const int k = kb[u] + sub;
-            if (k < ke[u]) {
-                col[u] = a.ci[k];
-                vv[u] = a.val[k];
-            }
+            const int kc = k < ke[u] ? k : 0;
+            col[u] = ci[kc];
+            vv[u] = val[kc];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            double xv = 0.0;
-            if (kb[u] + sub < ke[u]) xv = gather(col[u]);
-            acc[u] = vv[u] * xv;
+            const bool valid = kb[u] + sub < ke[u];
+            const double xv = gather(valid ? col[u] : 0);
+            acc[u] = valid ? vv[u] * xv : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -133,77 +146,29 @@ __global__ __launch_bounds__(kWG) void k_spmv(SpmvArgs a) {
             const int i = row[u];
             if (i >= r1 || sub != 0) continue;
             if (MODE == SPMV_DIR) {
-                const double pv = dir_value(beta, pold, a.z, i);
-                pnew[i] = pv;
+                pnew[i] = own[u];
                 a.q[i] = acc[u];
-                d0 += pv * acc[u];
+                d0 += own[u] * acc[u];
             } else if (MODE == SPMV_SIGMA) {
                 a.q[i] = acc[u];
-                d0 += pnew[i] * acc[u];
+                d0 += own[u] * acc[u];
             } else if (MODE == SPMV_RESID) {
-                const double bv = a.b[i];
-                const double rv = bv - acc[u];
+                const double rv = own[u] - acc[u];
                 a.r[i] = rv;
-                d0 += bv * bv;
+                d0 += own[u] * own[u];
                 d1 += rv * rv;
             } else {
                 const size_t at = (size_t)a.ls->j * a.ld + i;
-                const double v = a.zt[i] * invb;
-                a.V[at] = v;
+                a.V[at] = own[u];
                 if (a.has_m) a.U[at] = a.rt[i] * invb;
                 a.w[i] = acc[u];
-                d0 += v * acc[u];
+                d0 += own[u] * acc[u];
             }
         }
     }
 
-    double v[2] = {d0, d1}, out[2];
-    unsigned int *counter = (MODE == SPMV_LANCZOS) ? &a.ls->counter[0] : &a.st->counter[0];
-    if (!grid_sum<2>(v, a.partials, counter, out) || tid != 0) return;
-
-    if (MODE == SPMV_DIR || MODE == SPMV_SIGMA) {
-        PcgState *st = a.st;
-        const double sigma = out[0];
-        if (!(sigma > 0.0)) {
-            st->status = isfinite(sigma) ? BJP_EBREAKDOWN : BJP_ENONFINITE;
-            st->done = 1;
-        } else {
-            st->alpha = st->rho / sigma;
-        }
-    } else if (MODE == SPMV_RESID) {
-        PcgState *st = a.st;
-        const double bb = out[0], rr = out[1];
-        if (a.resid_phase == 0) {
-            st->bnorm2 = bb;
-            if (bb == 0.0) {
-                st->zero_rhs = 1;
-                st->relres = 0.0;
-                st->done = 1;
-            } else if (!isfinite(bb) || !isfinite(rr)) {
-                st->status = BJP_ENONFINITE;
-                st->done = 1;
-            } else {
-                const double relres = sqrt(rr) / sqrt(bb);
-                st->relres = relres;
-                if (a.hist && st->it == 0) a.hist[0] = relres;
-                if (relres <= st->tol) st->done = 1;
-            }
-        } else {
-            st->relres_true = (bb > 0.0) ? sqrt(rr) / sqrt(bb) : 0.0;
-        }
-    } else {
-        LanczosState *ls = a.ls;
-        const double al = out[0];
-        a.alpha_out[ls->j] = al;
-        ls->alpha_j = al;
-        if (!isfinite(al)) {
-            ls->status = BJP_ENONFINITE;
-            ls->steps_done = ls->j + 1;
-            ls->done = 1;
-        } else if (fabs(al) > ls->scale) {
-            ls->scale = fabs(al);
-        }
-    }
+    const double v[2] = {d0, d1};
+    block_partial<2>(v, a.partials);
 }
 
 // p_new = z + beta p_old for every row (the separate direction update used
