@@ -204,6 +204,16 @@ int bjp_kappa_estimate(const bjp_csr_t *A, const bjp_precond_t *M, const double 
                        int steps, double *alpha, double *beta, void *ws, size_t ws_bytes,
                        bjp_kappa_info_t *info /* host out */, hipStream_t stream);
 
+/* Gradient with respect to the stored values of A of a loss L(x), x = A^-1 b,
+ * given the adjoint lambda = A^-1 dL/dx (a second bjp_pcg_solve with rhs
+ * dL/dx, which is also dL/db): grad[k] = -lambda[i] * x[col_idx[k]] for every
+ * stored entry k of row i (the outer product -lambda x^T on A's pattern).
+ * lambda, x: device [n]; grad: device [nnz].  The CSR structure is trusted
+ * (validate it with bjp_precondition or bjp_pcg_solve first).  Asynchronous.
+ * (Differentiation through the solve; the paper's method has no gradient.) */
+int bjp_value_grad(const bjp_csr_t *A, const double *lambda, const double *x, double *grad,
+                   hipStream_t stream);
+
 /* Human-readable name of a status code (static storage). */
 const char *bjp_status_string(int status);
 

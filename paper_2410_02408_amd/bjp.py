@@ -111,6 +111,7 @@ def load():
     L.bjp_kappa_workspace.argtypes = [P(CsrT), C.c_int, P(sz)]
     L.bjp_kappa_estimate.argtypes = [P(CsrT), P(PrecondT), vp, C.c_int, vp, vp, vp, sz,
                                      P(KappaInfoT), vp]
+    L.bjp_value_grad.argtypes = [P(CsrT), vp, vp, vp, vp]
     _lib = L
     return L
 
@@ -336,3 +337,14 @@ def kappa_estimate(A: DeviceCsr, v0, steps: int, M: Precond | None = None,
     s = info.steps_done
     return KappaInfo(STATUS[info.status], s, info.theta_min, info.theta_max, info.kappa,
                      al[:s].cpu().numpy(), be[:max(s - 1, 0)].cpu().numpy())
+
+
+def value_grad(A: DeviceCsr, lam: torch.Tensor, x: torch.Tensor, out: torch.Tensor | None = None):
+    """bjp_value_grad: -lambda_i x_j on every stored entry of A (CSR order)."""
+    L = load()
+    g = torch.empty(A.nnz, dtype=torch.float64, device=A.device) if out is None else out
+    st = L.bjp_value_grad(C.byref(A.struct()), _ptr(_vec(lam, A.device)), _ptr(_vec(x, A.device)),
+                          _ptr(g), _stream(A.device))
+    if st:
+        raise BjpError(st, "bjp_value_grad")
+    return g

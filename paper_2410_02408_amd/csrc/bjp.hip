@@ -10,6 +10,7 @@
 #include <cstring>
 #include <vector>
 
+#include "adjoint.hpp"
 #include "bjp.h"
 #include "blocks.hpp"
 #include "common.hpp"
@@ -766,6 +767,31 @@ int bjp_kappa_estimate(const bjp_csr_t *A, const bjp_precond_t *M, const double 
     info->theta_max = h.theta_max;
     info->kappa = h.kappa;
     return h.status;
+}
+
+int bjp_value_grad(const bjp_csr_t *A, const double *lambda, const double *x, double *grad,
+                   hipStream_t stream) {
+    if (check_csr_host(A) != BJP_OK) return BJP_EINVAL;
+    if (A->n == 0 || A->nnz == 0) return BJP_OK;
+    if (!lambda || !x || !grad) return BJP_EINVAL;
+    const int gs = auto_lanes(A);
+    const int rows_per_step = kWG / gs;
+    const int grid = round8(std::min(ceil_div(A->n, rows_per_step * 4), 8192));
+    const int chunk = ceil_div(A->n, grid);
+    switch (gs) {
+#define BJP_VG(G)                                                                                   \
+    case G:                                                                                         \
+        hipLaunchKernelGGL((k_value_grad<G>), dim3(grid), dim3(kWG), 0, stream, A->n, chunk,        \
+                           A->row_ptr, A->col_idx, lambda, x, grad);                                 \
+        break;
+        BJP_VG(1) BJP_VG(2) BJP_VG(4) BJP_VG(8) BJP_VG(16) BJP_VG(32)
+        default:
+            hipLaunchKernelGGL((k_value_grad<64>), dim3(grid), dim3(kWG), 0, stream, A->n, chunk, A->row_ptr,
+                               A->col_idx, lambda, x, grad);
+#undef BJP_VG
+    }
+    HIP_TRY(hipGetLastError());
+    return BJP_OK;
 }
 
 }  // extern "C"
