@@ -204,6 +204,75 @@ int bjp_kappa_estimate(const bjp_csr_t *A, const bjp_precond_t *M, const double 
                        int steps, double *alpha, double *beta, void *ws, size_t ws_bytes,
                        bjp_kappa_info_t *info /* host out */, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Batches of independent systems (one persistent launch for the solve).
+ * The batch is a single block-diagonal CSR matrix: system s owns rows
+ * [sys_rows[s], sys_rows[s+1]) and every column of those rows must lie in
+ * the same range (checked).  Each system has its own uniform block size.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t num_systems;
+    const int32_t *sys_rows;     /* host [num_systems+1], sys_rows[0] = 0, last = n */
+    const int32_t *block_size;   /* host [num_systems], each 1..BJP_MAX_BLOCK */
+} bjp_batch_t;
+
+/* Batched preconditioner handle (points into the bjp_batch_precondition
+ * workspace). */
+typedef struct {
+    int32_t num_systems;
+    int32_t precision;           /* bjp_precision */
+    const void *systems;         /* device table, one record per system */
+    const void *tiles;           /* device, diagonal packets of every system */
+} bjp_batch_precond_t;
+
+typedef struct {
+    double tol;                  /* default 1e-10 */
+    int32_t max_iter;            /* per system, default its size */
+    int32_t max_replacements;    /* default 3; < 0 means none */
+    int32_t lanes;               /* lanes per CSR row: 0 = auto, else 4, 8, 16, 32 */
+    int32_t threads;             /* workgroup size: 0 = auto, else 256, 512, 1024 */
+    int32_t workgroups;          /* persistent workgroups: 0 = auto (2 per compute unit) */
+    int32_t pad;
+} bjp_batch_opts_t;
+
+/* Per-system result (same layout as the device record the solver writes). */
+typedef struct {
+    int32_t status, iterations, replacements, pad;
+    double rel_res_recursive, rel_res_true;
+} bjp_system_info_t;
+
+typedef struct {
+    int32_t status;              /* BJP_OK if every system converged, else the first failure */
+    int32_t systems_ok;
+    int32_t max_iterations;
+    int32_t pad;
+    int64_t total_iterations;    /* sum over systems */
+    double max_rel_res_true;
+} bjp_batch_info_t;
+
+int bjp_batch_precondition_workspace(const bjp_csr_t *A, const bjp_batch_t *B, int precision,
+                                     size_t *bytes /* host out */);
+
+/* Per-system block-Jacobi setup (the same extraction, Cholesky and inverse as
+ * bjp_precondition) for every system of the batch.  *failed_block receives the
+ * global index (counting blocks system by system) of the first non-SPD block.
+ * Synchronises `stream`. */
+int bjp_batch_precondition(const bjp_csr_t *A, const bjp_batch_t *B, int precision, void *ws,
+                           size_t ws_bytes, bjp_batch_precond_t *M_out /* host out */,
+                           int32_t *failed_block /* host out */, hipStream_t stream);
+
+int bjp_batch_pcg_workspace(const bjp_csr_t *A, const bjp_batch_t *B, size_t *bytes /* host out */);
+
+/* Solve every system of the batch with PCG (the algorithm and stopping rule of
+ * bjp_pcg_solve, x0 = 0) in one persistent launch: each workgroup takes the
+ * next unsolved system, largest first, and iterates it to convergence.
+ * b, x: device [n].  per_system (host [num_systems], optional) receives each
+ * system's result.  Synchronises `stream`. */
+int bjp_batch_pcg_solve(const bjp_csr_t *A, const bjp_batch_t *B, const bjp_batch_precond_t *M,
+                        const double *b, double *x, const bjp_batch_opts_t *opts, void *ws,
+                        size_t ws_bytes, bjp_batch_info_t *info /* host out */,
+                        bjp_system_info_t *per_system /* host out, optional */, hipStream_t stream);
+
 /* Gradient with respect to the stored values of A of a loss L(x), x = A^-1 b,
  * given the adjoint lambda = A^-1 dL/dx (a second bjp_pcg_solve with rhs
  * dL/dx, which is also dL/db): grad[k] = -lambda[i] * x[col_idx[k]] for every

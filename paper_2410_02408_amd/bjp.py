@@ -348,3 +348,151 @@ def value_grad(A: DeviceCsr, lam: torch.Tensor, x: torch.Tensor, out: torch.Tens
     if st:
         raise BjpError(st, "bjp_value_grad")
     return g
+
+
+# ---------------------------------------------------------------------------
+# batches of independent systems
+# ---------------------------------------------------------------------------
+
+class BatchT(C.Structure):
+    _fields_ = [("num_systems", C.c_int32), ("sys_rows", C.c_void_p), ("block_size", C.c_void_p)]
+
+
+class BatchPrecondT(C.Structure):
+    _fields_ = [("num_systems", C.c_int32), ("precision", C.c_int32), ("systems", C.c_void_p),
+                ("tiles", C.c_void_p)]
+
+
+class BatchOptsT(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("max_replacements", C.c_int32),
+                ("lanes", C.c_int32), ("threads", C.c_int32), ("workgroups", C.c_int32),
+                ("pad", C.c_int32)]
+
+
+class SystemInfoT(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("replacements", C.c_int32),
+                ("pad", C.c_int32), ("rel_res_recursive", C.c_double), ("rel_res_true", C.c_double)]
+
+
+class BatchInfoT(C.Structure):
+    _fields_ = [("status", C.c_int32), ("systems_ok", C.c_int32), ("max_iterations", C.c_int32),
+                ("pad", C.c_int32), ("total_iterations", C.c_int64), ("max_rel_res_true", C.c_double)]
+
+
+def _load_batch(L):
+    if getattr(L, "_batch_ready", False):
+        return L
+    P = C.POINTER
+    vp, sz = C.c_void_p, C.c_size_t
+    L.bjp_batch_precondition_workspace.argtypes = [P(CsrT), P(BatchT), C.c_int, P(sz)]
+    L.bjp_batch_precondition.argtypes = [P(CsrT), P(BatchT), C.c_int, vp, sz, P(BatchPrecondT),
+                                         P(C.c_int32), vp]
+    L.bjp_batch_pcg_workspace.argtypes = [P(CsrT), P(BatchT), P(sz)]
+    L.bjp_batch_pcg_solve.argtypes = [P(CsrT), P(BatchT), P(BatchPrecondT), vp, vp, P(BatchOptsT), vp,
+                                      sz, P(BatchInfoT), vp, vp]
+    L._batch_ready = True
+    return L
+
+
+class Batch:
+    """A batch of independent systems stored as one block-diagonal CSR on
+    the device (system s = rows sys_rows[s]:sys_rows[s+1]) with a block size
+    per system."""
+
+    def __init__(self, A: DeviceCsr, sys_rows, block_sizes):
+        self.A = A
+        self.sys_rows = np.ascontiguousarray(sys_rows, dtype=np.int32)
+        self.block_sizes = np.ascontiguousarray(block_sizes, dtype=np.int32)
+        self.num_systems = len(self.block_sizes)
+
+    @classmethod
+    def from_systems(cls, mats, block_sizes, device="cuda"):
+        """Concatenate host CSR systems (columns shifted to global rows)."""
+        rows = np.zeros(len(mats) + 1, dtype=np.int64)
+        for s, M in enumerate(mats):
+            rows[s + 1] = rows[s] + M.n
+        nnz = np.zeros(len(mats) + 1, dtype=np.int64)
+        for s, M in enumerate(mats):
+            nnz[s + 1] = nnz[s] + M.nnz
+        rp = np.empty(int(rows[-1]) + 1, dtype=np.int64)
+        ci = np.empty(int(nnz[-1]), dtype=np.int32)
+        va = np.empty(int(nnz[-1]), dtype=np.float64)
+        for s, M in enumerate(mats):
+            rp[rows[s]:rows[s + 1]] = M.row_ptr[:-1].astype(np.int64) + nnz[s]
+            ci[nnz[s]:nnz[s + 1]] = M.col_idx + rows[s]
+            va[nnz[s]:nnz[s + 1]] = M.val
+        rp[-1] = nnz[-1]
+        if nnz[-1] >= 2 ** 31:
+            raise ValueError("batch nnz does not fit int32 indices")
+        dev = torch.device(device)
+        A = DeviceCsr(int(rows[-1]), torch.as_tensor(rp.astype(np.int32), device=dev),
+                      torch.as_tensor(ci, device=dev), torch.as_tensor(va, device=dev))
+        return cls(A, rows.astype(np.int32), block_sizes)
+
+    def struct(self) -> BatchT:
+        return BatchT(self.num_systems, self.sys_rows.ctypes.data, self.block_sizes.ctypes.data)
+
+
+class BatchPrecond:
+    def __init__(self, handle: BatchPrecondT, ws: torch.Tensor):
+        self.handle = handle
+        self.ws = ws
+
+
+def batch_precondition(B: Batch, precision: str | int = "fp64") -> BatchPrecond:
+    """bjp_batch_precondition: per-system block-Jacobi setup for the whole batch."""
+    L = _load_batch(load())
+    prec = {"fp64": FP64, "fp32": FP32_STORE}.get(precision, precision)
+    csr, bs = B.A.struct(), B.struct()
+    n = C.c_size_t()
+    st = L.bjp_batch_precondition_workspace(C.byref(csr), C.byref(bs), prec, C.byref(n))
+    if st:
+        raise BjpError(st, "bjp_batch_precondition_workspace")
+    ws = _workspace(n.value, B.A.device)
+    h = BatchPrecondT()
+    fb = C.c_int32(-1)
+    st = L.bjp_batch_precondition(C.byref(csr), C.byref(bs), prec, _ptr(ws), ws.numel(), C.byref(h),
+                                  C.byref(fb), _stream(B.A.device))
+    if st:
+        raise BjpError(st, "bjp_batch_precondition", fb.value)
+    return BatchPrecond(h, ws)
+
+
+@dataclasses.dataclass
+class BatchInfo:
+    status: str
+    systems_ok: int
+    total_iterations: int
+    max_iterations: int
+    max_rel_res_true: float
+    per_system: np.ndarray      # structured: status, iterations, replacements, rel_res_*
+
+
+def batch_pcg_solve(B: Batch, M: BatchPrecond, b, tol: float = 1e-10, max_iter: int = 0,
+                    lanes: int = 0, threads: int = 0, workgroups: int = 0,
+                    out: torch.Tensor | None = None, workspace: torch.Tensor | None = None):
+    """bjp_batch_pcg_solve: all systems in one persistent launch."""
+    L = _load_batch(load())
+    dev = B.A.device
+    b = _vec(b, dev)
+    x = torch.empty(B.A.n, dtype=torch.float64, device=dev) if out is None else out
+    csr, bs = B.A.struct(), B.struct()
+    if workspace is None:
+        n = C.c_size_t()
+        st = L.bjp_batch_pcg_workspace(C.byref(csr), C.byref(bs), C.byref(n))
+        if st:
+            raise BjpError(st, "bjp_batch_pcg_workspace")
+        workspace = _workspace(n.value, dev)
+    opts = BatchOptsT(tol, int(max_iter), 0, int(lanes), int(threads), int(workgroups), 0)
+    info = BatchInfoT()
+    per = (SystemInfoT * B.num_systems)()
+    st = L.bjp_batch_pcg_solve(C.byref(csr), C.byref(bs), C.byref(M.handle), _ptr(b), _ptr(x),
+                               C.byref(opts), _ptr(workspace), workspace.numel(), C.byref(info),
+                               C.cast(per, C.c_void_p), _stream(dev))
+    if st in (-1, -6, -7):
+        raise BjpError(st, "bjp_batch_pcg_solve")
+    arr = np.array([(p.status, p.iterations, p.replacements, p.rel_res_recursive, p.rel_res_true)
+                    for p in per], dtype=[("status", "i4"), ("iterations", "i4"), ("replacements", "i4"),
+                                          ("rel_res_recursive", "f8"), ("rel_res_true", "f8")])
+    return x, BatchInfo(STATUS[info.status], info.systems_ok, info.total_iterations,
+                        info.max_iterations, info.max_rel_res_true, arr)

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "adjoint.hpp"
+#include "batch.hpp"
 #include "bjp.h"
 #include "blocks.hpp"
 #include "common.hpp"
@@ -302,6 +303,76 @@ int auto_lanes(const bjp_csr_t *A) {
     return gs;
 }
 
+// ---------------------------------------------------------------------------
+// batches
+// ---------------------------------------------------------------------------
+struct BatchPlan {
+    std::vector<SysInfo> sys;
+    std::vector<int32_t> off;        // per system: nblocks+1 global row offsets
+    std::vector<long long> off_base; // index of each system's first offset
+    std::vector<int> block_base;     // global index of each system's first block
+    size_t tile_scalars = 0;
+};
+
+int make_batch_plan(const bjp_csr_t *A, const bjp_batch_t *B, BatchPlan &P) {
+    if (!B || B->num_systems <= 0 || !B->sys_rows || !B->block_size) return BJP_EINVAL;
+    const int S = B->num_systems;
+    if (B->sys_rows[0] != 0 || B->sys_rows[S] != A->n) return BJP_EINVAL;
+    P.sys.resize(S);
+    P.off.clear();
+    P.off_base.resize(S);
+    P.block_base.resize(S);
+    long long tiles = 0;
+    int blocks = 0;
+    for (int s = 0; s < S; ++s) {
+        const int r0 = B->sys_rows[s], r1 = B->sys_rows[s + 1], nb = B->block_size[s];
+        if (r1 <= r0 || nb < 1 || nb > BJP_MAX_BLOCK) return BJP_EINVAL;
+        SysInfo &si = P.sys[s];
+        si.row0 = r0;
+        si.n = r1 - r0;
+        si.nb = nb;
+        si.G = pow2_at_least(std::min(nb, si.n));
+        si.nblocks = ceil_div(si.n, nb);
+        si.packets = ceil_div(si.nblocks, 64 / si.G);
+        si.tile0 = tiles;
+        tiles += (long long)si.packets * packet_elems(si.G);
+        P.off_base[s] = (long long)P.off.size();
+        P.block_base[s] = blocks;
+        blocks += si.nblocks;
+        for (long long r = r0; r < r1; r += nb) P.off.push_back((int32_t)r);
+        P.off.push_back(r1);
+    }
+    P.tile_scalars = (size_t)tiles;
+    return BJP_OK;
+}
+
+size_t batch_precond_bytes(const BatchPlan &P, int precision) {
+    const size_t elem = precision == BJP_FP32_STORE ? 4 : 8;
+    return al256(sizeof(SysInfo) * P.sys.size()) + al256(sizeof(int32_t) * (P.sys.size() + 1)) +
+           al256(sizeof(int32_t) * P.off.size()) + al256(P.tile_scalars * elem) + al256(64);
+}
+
+template <int NT, typename TS>
+void launch_batch_nt(int gs, int grid, const BatchArgs &a, hipStream_t s) {
+    switch (gs) {
+        case 4: hipLaunchKernelGGL((k_pcg_batch<NT, 4, TS>), dim3(grid), dim3(NT), 0, s, a); break;
+        case 8: hipLaunchKernelGGL((k_pcg_batch<NT, 8, TS>), dim3(grid), dim3(NT), 0, s, a); break;
+        case 16: hipLaunchKernelGGL((k_pcg_batch<NT, 16, TS>), dim3(grid), dim3(NT), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_pcg_batch<NT, 32, TS>), dim3(grid), dim3(NT), 0, s, a); break;
+    }
+}
+
+template <typename TS>
+void launch_batch(int nt, int gs, int grid, const BatchArgs &a, hipStream_t s) {
+    if (nt == 256) launch_batch_nt<256, TS>(gs, grid, a, s);
+    else if (nt == 1024) launch_batch_nt<1024, TS>(gs, grid, a, s);
+    else launch_batch_nt<512, TS>(gs, grid, a, s);
+}
+
+__global__ void k_zero_int(int *p) {
+    if (threadIdx.x == 0) *p = 0;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -371,7 +442,7 @@ int bjp_precondition(const bjp_csr_t *A, const bjp_block_spec_t *spec, int preci
 
     HIP_TRY(hipMemcpyAsync(off, P.off.data(), sizeof(int32_t) * P.off.size(), hipMemcpyHostToDevice,
                            stream));
-    SetupArgs sa{A->row_ptr, A->col_idx, A->val, off, P.nblocks, tiles, flags};
+    SetupArgs sa{A->row_ptr, A->col_idx, A->val, off, P.nblocks, tiles, flags, 0};
     if (precision == BJP_FP32_STORE) launch_setup<float>(P.G, P.packets, sa, stream);
     else launch_setup<double>(P.G, P.packets, sa, stream);
     HIP_TRY(hipGetLastError());
@@ -767,6 +838,178 @@ int bjp_kappa_estimate(const bjp_csr_t *A, const bjp_precond_t *M, const double 
     info->theta_max = h.theta_max;
     info->kappa = h.kappa;
     return h.status;
+}
+
+int bjp_batch_precondition_workspace(const bjp_csr_t *A, const bjp_batch_t *B, int precision,
+                                     size_t *bytes) {
+    if (!bytes) return BJP_EINVAL;
+    *bytes = 0;
+    if (check_csr_host(A) != BJP_OK) return BJP_EINVAL;
+    if (precision != BJP_FP64 && precision != BJP_FP32_STORE) return BJP_EINVAL;
+    BatchPlan P;
+    const int st = make_batch_plan(A, B, P);
+    if (st != BJP_OK) return st;
+    *bytes = batch_precond_bytes(P, precision);
+    return BJP_OK;
+}
+
+int bjp_batch_precondition(const bjp_csr_t *A, const bjp_batch_t *B, int precision, void *ws,
+                           size_t ws_bytes, bjp_batch_precond_t *M_out, int32_t *failed_block,
+                           hipStream_t stream) {
+    if (failed_block) *failed_block = -1;
+    if (!M_out) return BJP_EINVAL;
+    std::memset(M_out, 0, sizeof(*M_out));
+    if (check_csr_host(A) != BJP_OK) return BJP_EINVAL;
+    if (precision != BJP_FP64 && precision != BJP_FP32_STORE) return BJP_EINVAL;
+    BatchPlan P;
+    int st = make_batch_plan(A, B, P);
+    if (st != BJP_OK) return st;
+    if (!ws || ws_bytes < batch_precond_bytes(P, precision) || (reinterpret_cast<uintptr_t>(ws) & 255))
+        return BJP_EWORKSPACE;
+    const int S = B->num_systems;
+    const size_t elem = precision == BJP_FP32_STORE ? 4 : 8;
+    Carver cv{static_cast<char *>(ws)};
+    SysInfo *sys = cv.take<SysInfo>(S);
+    int32_t *rows = cv.take<int32_t>(S + 1);
+    int32_t *off = cv.take<int32_t>(P.off.size());
+    char *tiles = cv.base + cv.used;
+    cv.used += al256(P.tile_scalars * elem);
+    int32_t *flags = cv.take<int32_t>(16);
+    M_out->num_systems = S;
+    M_out->precision = precision;
+    M_out->systems = sys;
+    M_out->tiles = tiles;
+
+    st = run_validate(A, flags, stream);
+    if (st != BJP_OK) return st;
+    HIP_TRY(hipMemcpyAsync(sys, P.sys.data(), sizeof(SysInfo) * S, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(rows, B->sys_rows, sizeof(int32_t) * (S + 1), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(off, P.off.data(), sizeof(int32_t) * P.off.size(), hipMemcpyHostToDevice, stream));
+    hipLaunchKernelGGL(k_validate_batch, dim3(std::min(S, 4096)), dim3(kWG), 0, stream, S, rows,
+                       A->row_ptr, A->col_idx, flags);
+    for (int s = 0; s < S; ++s) {
+        const SysInfo &si = P.sys[s];
+        SetupArgs sa{A->row_ptr, A->col_idx, A->val, off + P.off_base[s], si.nblocks,
+                     tiles + (size_t)si.tile0 * elem, flags, P.block_base[s]};
+        if (precision == BJP_FP32_STORE) launch_setup<float>(si.G, si.packets, sa, stream);
+        else launch_setup<double>(si.G, si.packets, sa, stream);
+    }
+    HIP_TRY(hipGetLastError());
+    int32_t h[4];
+    HIP_TRY(hipMemcpyAsync(h, flags, sizeof(h), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    if (h[1]) return BJP_EINVAL;
+    if (h[0] != INT_MAX) {
+        if (failed_block) *failed_block = h[0];
+        return BJP_ENOTSPD;
+    }
+    return BJP_OK;
+}
+
+int bjp_batch_pcg_workspace(const bjp_csr_t *A, const bjp_batch_t *B, size_t *bytes) {
+    if (!bytes) return BJP_EINVAL;
+    *bytes = 0;
+    if (check_csr_host(A) != BJP_OK || !B || B->num_systems <= 0) return BJP_EINVAL;
+    const size_t S = (size_t)B->num_systems;
+    *bytes = 4 * al256(sizeof(double) * (size_t)std::max(A->n, 1)) + al256(sizeof(int) * S) +
+             al256(sizeof(SysOut) * S) + 2 * al256(64);
+    return BJP_OK;
+}
+
+int bjp_batch_pcg_solve(const bjp_csr_t *A, const bjp_batch_t *B, const bjp_batch_precond_t *M,
+                        const double *b, double *x, const bjp_batch_opts_t *opts, void *ws,
+                        size_t ws_bytes, bjp_batch_info_t *info, bjp_system_info_t *per_system,
+                        hipStream_t stream) {
+    if (!info) return BJP_EINVAL;
+    std::memset(info, 0, sizeof(*info));
+    auto fail = [&](int st) {
+        info->status = st;
+        return st;
+    };
+    static_assert(sizeof(SysOut) == sizeof(bjp_system_info_t), "per-system record layout");
+    if (check_csr_host(A) != BJP_OK || !M || !b || !x || A->n <= 0 || A->nnz <= 0) return fail(BJP_EINVAL);
+    BatchPlan P;
+    int st = make_batch_plan(A, B, P);
+    if (st != BJP_OK) return fail(st);
+    const int S = B->num_systems;
+    if (M->num_systems != S || !M->systems || !M->tiles) return fail(BJP_EINVAL);
+    size_t need = 0;
+    bjp_batch_pcg_workspace(A, B, &need);
+    if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255)) return fail(BJP_EWORKSPACE);
+    bjp_batch_opts_t o{};
+    if (opts) o = *opts;
+    if (!(o.tol > 0.0)) o.tol = 1e-10;
+    if (o.max_replacements == 0) o.max_replacements = 3;
+    else if (o.max_replacements < 0) o.max_replacements = 0;
+    int max_n = 0;
+    for (const SysInfo &si : P.sys) max_n = std::max(max_n, si.n);
+    if (o.max_iter <= 0) o.max_iter = max_n;
+    int gs = o.lanes;
+    if (gs <= 0) gs = std::min(32, std::max(4, auto_lanes(A)));
+    gs = std::min(32, std::max(4, pow2_at_least(gs)));
+    const int nt = (o.threads == 256 || o.threads == 1024) ? o.threads : 512;
+    int grid = o.workgroups;
+    if (grid <= 0) {
+        int dev = 0, cus = 256;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            hipDeviceProp_t prop;
+            if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+        }
+        grid = 2 * cus;
+    }
+    grid = std::max(1, std::min(grid, S));
+
+    Carver cv{static_cast<char *>(ws)};
+    double *r = cv.take<double>(A->n), *z = cv.take<double>(A->n);
+    double *p = cv.take<double>(A->n), *q = cv.take<double>(A->n);
+    int *order = cv.take<int>(S);
+    SysOut *out = cv.take<SysOut>(S);
+    int *queue = cv.take<int>(16);
+    int32_t *flags = cv.take<int32_t>(16);
+
+    st = run_validate(A, flags, stream);
+    if (st != BJP_OK) return fail(st);
+    std::vector<int> ord(S);
+    for (int s = 0; s < S; ++s) ord[s] = s;
+    std::stable_sort(ord.begin(), ord.end(), [&](int u, int v) { return P.sys[u].n > P.sys[v].n; });
+    HIP_TRY(hipMemcpyAsync(order, ord.data(), sizeof(int) * S, hipMemcpyHostToDevice, stream));
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, stream, queue);
+
+    BatchArgs a{};
+    a.S = S;
+    a.sys = static_cast<const SysInfo *>(M->systems);
+    a.order = order;
+    a.queue = queue;
+    a.rp = A->row_ptr;
+    a.ci = A->col_idx;
+    a.val = A->val;
+    a.b = b;
+    a.x = x;
+    a.r = r;
+    a.z = z;
+    a.p = p;
+    a.q = q;
+    a.tiles = M->tiles;
+    a.tol = o.tol;
+    a.max_iter = o.max_iter;
+    a.max_repl = o.max_replacements;
+    a.out = out;
+    if (M->precision == BJP_FP32_STORE) launch_batch<float>(nt, gs, grid, a, stream);
+    else launch_batch<double>(nt, gs, grid, a, stream);
+    HIP_TRY(hipGetLastError());
+    std::vector<SysOut> h(S);
+    HIP_TRY(hipMemcpyAsync(h.data(), out, sizeof(SysOut) * S, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    info->status = BJP_OK;
+    for (int s = 0; s < S; ++s) {
+        if (h[s].status == BJP_OK) info->systems_ok++;
+        else if (info->status == BJP_OK) info->status = h[s].status;
+        info->total_iterations += h[s].iterations;
+        info->max_iterations = std::max(info->max_iterations, h[s].iterations);
+        info->max_rel_res_true = std::max(info->max_rel_res_true, h[s].relres_true);
+    }
+    if (per_system) std::memcpy(per_system, h.data(), sizeof(SysOut) * S);
+    return info->status;
 }
 
 int bjp_value_grad(const bjp_csr_t *A, const double *lambda, const double *x, double *grad,

@@ -38,6 +38,7 @@ struct SetupArgs {
     int nblocks;
     void *tiles;
     int32_t *flags;         // [0]: first failing block (INT_MAX if none)
+    int block_base;         // added to the reported block index (batches)
 };
 
 template <int G, typename TS>
@@ -82,7 +83,7 @@ __global__ __launch_bounds__(64) void k_setup(SetupArgs a) {
         if (i == j && j < n) Tg[j][j] = ljj;
         __syncthreads();
     }
-    if (!ok) atomicMin(&a.flags[0], t);
+    if (!ok) atomicMin(&a.flags[0], a.block_base + t);
 
     // 3. W = L^-1 (lower); lane c computes column c, stored transposed in the
     //    strict upper triangle (W[k][c] at T[c][k]), diagonal 1/L_cc in Wd.
@@ -130,6 +131,47 @@ __global__ __launch_bounds__(64) void k_setup(SetupArgs a) {
 // ---------------------------------------------------------------------------
 // Application
 // ---------------------------------------------------------------------------
+#ifndef BJP_APPLY_CHUNK
+#define BJP_APPLY_CHUNK 32
+#endif
+
+// z_i of one lane for one packet: D = the packet, rs = this lane's r (0 when
+// inactive), n = the lane's block size, i = lane index in its group.  The
+// diagonals are streamed KC at a time (a scheduling barrier between chunks
+// keeps at most KC of them live), so register use stays bounded for G = 64.
+template <int G, typename TS, int KC = BJP_APPLY_CHUNK>
+__device__ __forceinline__ TS packet_apply(const TS *__restrict__ D, int lane, int g, int i, int n, TS rs) {
+    constexpr int K = G / 2;
+    const bool act = i < n;
+    const int ia = act ? i : 0;
+    const int nn = n > 0 ? n : 1;
+    TS zv = D[lane] * rs;
+#pragma unroll
+    for (int k0 = 1; k0 <= K; k0 += KC) {
+        TS dv[KC];
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) {
+            const int k = k0 + kk;
+            if (k <= K) dv[kk] = k < K ? D[k * 64 + lane] : D[K * 64 + g * K + (i & (K - 1))];
+        }
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) {
+            const int k = k0 + kk;
+            if (k > K) break;
+            int j1 = ia + k;
+            if (j1 >= nn) j1 -= nn;
+            int j2 = ia - k;
+            if (j2 < 0) j2 += nn;
+            const TS rk = __shfl(rs, g * G + (j1 & (G - 1)), 64);
+            if (act && 2 * k <= n) zv += dv[kk] * rk;
+            const TS tv = (act && 2 * k < n) ? dv[kk] * rs : (TS)0;
+            const TS tt = __shfl(tv, g * G + (j2 & (G - 1)), 64);
+            if (act && 2 * k < n) zv += tt;
+        }
+        if (k0 + KC <= K) __builtin_amdgcn_sched_barrier(0);
+    }
+    return zv;
+}
 enum ApplyMode { APPLY_PLAIN = 0, APPLY_INIT = 1, APPLY_UPDATE = 2, APPLY_LANCZOS = 3 };
 
 struct ApplyArgs {
@@ -156,7 +198,7 @@ __global__ __launch_bounds__(kWG) void k_apply(ApplyArgs a) {
     if (MODE == APPLY_LANCZOS) {
         if (a.ls->done) return;
     }
-    constexpr int P = 64 / G, E = packet_elems(G), K = G / 2;
+    constexpr int P = 64 / G, E = packet_elems(G);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane / G, i = lane % G;
     const int c = xcd_chunk(blockIdx.x, gridDim.x);
@@ -178,14 +220,6 @@ __global__ __launch_bounds__(kWG) void k_apply(ApplyArgs a) {
     double *__restrict__ zout = a.zout;
     double d0 = 0.0, d1 = 0.0;
     for (int pk = pk0 + wave; pk < pk1; pk += kWaves) {
-        // The packet's diagonals are issued first: they are the bulk of the
-        // bytes and do not depend on anything else in the iteration.
-        const TS *D = tiles + (size_t)pk * E;
-        TS dv[K + 1];
-        dv[0] = D[lane];
-#pragma unroll
-        for (int k = 1; k <= K; ++k) dv[k] = k < K ? D[k * 64 + lane] : D[K * 64 + g * K + (i & (K - 1))];
-
         const int t = pk * P + g;
         int s = 0, n = 0;
         if (a.uniform_nb > 0) {
@@ -212,23 +246,7 @@ __global__ __launch_bounds__(kWG) void k_apply(ApplyArgs a) {
             const double ro = rin[rc];
             rv = act ? ro : 0.0;
         }
-        const TS rs = (TS)rv;
-        TS zv = dv[0] * rs;
-        const int ia = act ? i : 0;
-        const int nn = n > 0 ? n : 1;
-#pragma unroll
-        for (int k = 1; k <= K; ++k) {
-            const TS v = dv[k];
-            int j1 = ia + k;
-            if (j1 >= nn) j1 -= nn;
-            int j2 = ia - k;
-            if (j2 < 0) j2 += nn;
-            const TS rk = __shfl(rs, g * G + (j1 & (G - 1)), 64);
-            if (act && 2 * k <= n) zv += v * rk;
-            const TS tv = (act && 2 * k < n) ? v * rs : (TS)0;
-            const TS tt = __shfl(tv, g * G + (j2 & (G - 1)), 64);
-            if (act && 2 * k < n) zv += tt;
-        }
+        const TS zv = packet_apply<G, TS>(tiles + (size_t)pk * E, lane, g, i, n, (TS)rv);
         if (act) {
             const double z = (double)zv;
             zout[row] = z;
