@@ -36,6 +36,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=40)
     ap.add_argument("--kappa-steps", type=int, default=0, help="override Lanczos steps (0 = workload's)")
+    ap.add_argument("--mode", default="headline",
+                    choices=["headline", "nb_sweep", "batch", "adjoint", "precision"],
+                    help="headline: the metric's line; the others measure the extensions")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     return ap.parse_args()
 
 
@@ -73,12 +77,178 @@ def read_traffic(kernel_tag: str):
     return float(t.group(1))
 
 
+def _timed(fn):
+    import torch
+
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    out = fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return out, e0.elapsed_time(e1)
+
+
+def mode_nb_sweep(args):
+    """kappa(M^-1 A), PCG iterations and time per block size (the paper's
+    block-size question, answered by measurement; n_b = 1 is its point Jacobi)."""
+    import numpy as np
+    import torch
+
+    from paper_2410_02408_amd import bjp, workloads
+
+    W = workloads.workload(args.workload)
+    steps = args.kappa_steps or W.lanczos_steps
+    dev = torch.device("cuda:0")
+    A = bjp.DeviceCsr.from_host(W.A, dev)
+    b = torch.as_tensor(W.b, device=dev)
+    ws = bjp.PcgWorkspace(A)
+    kws = bjp.KappaWorkspace(A, steps)
+    kA = bjp.kappa_estimate(A, b, steps, None, workspace=kws)
+    for nb in (1, 8, 16, 32, 64):
+        M, setup_ms = _timed(lambda: bjp.precondition(A, block_size=nb, precision=args.precision))
+        bjp.pcg_solve(A, M, b, tol=W.tol, workspace=ws)
+        (x, info), ms = _timed(lambda: bjp.pcg_solve(A, M, b, tol=W.tol, workspace=ws))
+        k = bjp.kappa_estimate(A, b, steps, M, workspace=kws)
+        print(json.dumps({"mode": "nb_sweep", "workload": args.workload, "block_size": nb,
+                          "precision": args.precision, "kappa_A": kA.kappa, "kappa_MA": k.kappa,
+                          "lanczos_steps": steps, "pcg_iterations": info.iterations,
+                          "pcg_ms": round(ms, 3), "us_per_iteration": round(1e3 * ms / info.iterations, 2),
+                          "setup_ms": round(setup_ms, 3), "rel_res_true": info.rel_res_true,
+                          "status": info.status}), flush=True)
+
+
+def mode_batch(args):
+    """512 uneven random SPD systems solved in one persistent launch."""
+    import numpy as np
+    import torch
+
+    from paper_2410_02408_amd import autotune, bjp, workloads
+
+    t0 = time.time()
+    mats, nbs, rhs = workloads.random_spd_batch(512, seed=2)
+    gen_s = time.time() - t0
+    dev = torch.device("cuda:0")
+    B = bjp.Batch.from_systems(mats, nbs, dev)
+    b = torch.as_tensor(np.concatenate(rhs), device=dev)
+    M, setup_ms = _timed(lambda: bjp.batch_precondition(B, precision=args.precision))
+    cfg, timings = autotune.tune_batch(B, M, b, probe_iters=10)
+    bjp.batch_pcg_solve(B, M, b, **cfg)
+    (x, info), ms = _timed(lambda: bjp.batch_pcg_solve(B, M, b, **cfg))
+    n = np.diff(B.sys_rows.astype(np.int64))
+    nnz = np.array([m.nnz for m in mats], dtype=np.int64)
+    nbv = np.array(nbs, dtype=np.int64)
+    it = info.per_system["iterations"].astype(np.int64)
+    msz = 4 if args.precision == "fp32" else 8
+    # per system per iteration: CSR, packed inverses, vectors (x,p,r,q,z traffic
+    # of the workgroup-phased iteration: p,z rd + p wr; p gathered, q wr;
+    # x,p,q,r rd + x,r,z wr)
+    per_it = 12 * nnz + 4 * n + msz * n * (nbv + 1) // 2 + 88 * n
+    total_bytes = float(np.sum(per_it * it))
+    print(json.dumps({"mode": "batch", "workload": "random_spd_batch_512", "precision": args.precision,
+                      "systems": len(mats), "rows_total": int(n.sum()), "nnz_total": int(nnz.sum()),
+                      "status": info.status, "systems_ok": info.systems_ok,
+                      "total_iterations": int(info.total_iterations), "max_iterations": info.max_iterations,
+                      "solve_ms": round(ms, 3),
+                      "system_iterations_per_s": round(info.total_iterations / (ms / 1e3), 1),
+                      "achieved_gbps": round(total_bytes / (ms / 1e3) / 1e9, 1),
+                      "max_rel_res_true": info.max_rel_res_true, "setup_ms": round(setup_ms, 3),
+                      "launch": cfg, "gen_s": round(gen_s, 1)}), flush=True)
+
+
+def mode_adjoint(args):
+    """Forward + adjoint solve on the 2D edge-conductivity Poisson problem."""
+    import numpy as np
+    import torch
+
+    from paper_2410_02408_amd import autograd as ad, workloads
+
+    n = 1024
+    g = workloads.edge_graph2d(n)
+    c = workloads.edge_conductivities(g, seed=3)
+    A = workloads.edge_poisson2d(g, c)
+    b, xt = workloads.rhs(A.n, 3), workloads.target(A.n, 3)
+    dev = torch.device("cuda:0")
+    pat = ad.Pattern.from_host(A, dev)
+    asm = ad.EdgeAssembly(g, A, dev)
+    ct = torch.as_tensor(c, device=dev).requires_grad_(True)
+    bt = torch.as_tensor(b, device=dev).requires_grad_(True)
+    xtt = torch.as_tensor(xt, device=dev)
+
+    def run():
+        infos = []
+        x = ad.pcg_solve_diff(asm.assemble(ct), bt, pat, 32, tol=1e-10, info_out=infos)
+        loss = torch.sum((x - xtt) ** 2)
+        loss.backward()
+        return infos, loss
+
+    run()
+    ct.grad = None
+    bt.grad = None
+    (infos, loss), ms = _timed(run)
+    its = [i.iterations for i in infos]
+    print(json.dumps({"mode": "adjoint", "workload": "edge_poisson2d_1024", "n": A.n, "nnz": A.nnz,
+                      "block_size": 32, "forward_iterations": its[0], "adjoint_iterations": its[1],
+                      "forward_plus_backward_ms": round(ms, 3),
+                      "pcg_iterations_per_s": round(sum(its) / (ms / 1e3), 1),
+                      "loss": loss.item(), "grad_c_norm": float(ct.grad.norm()),
+                      "status": [i.status for i in infos]}), flush=True)
+
+
+def mode_precision(args):
+    """FP32-stored block inverses inside the FP64 PCG vs the plain FP64 path,
+    both to the 1e-10 true residual, on the power-law workload."""
+    import numpy as np
+    import torch
+
+    from paper_2410_02408_amd import bjp, workloads
+
+    t0 = time.time()
+    A_h = workloads.powerlaw_spd(1 << 22, seed=4)
+    b_h = workloads.rhs(A_h.n, 4)
+    gen_s = time.time() - t0
+    dev = torch.device("cuda:0")
+    A = bjp.DeviceCsr.from_host(A_h, dev)
+    b = torch.as_tensor(b_h, device=dev)
+    ws = bjp.PcgWorkspace(A)
+    deg = np.diff(A_h.row_ptr)
+    res = {}
+    for prec in ("fp64", "fp32"):
+        M, setup_ms = _timed(lambda: bjp.precondition(A, block_size=32, precision=prec))
+        bjp.pcg_solve(A, M, b, workspace=ws)
+        tm = bjp.KernelTimer(bjp.KERNEL_APPLY, 4096)
+        (x, info), ms = _timed(lambda: bjp.pcg_solve(A, M, b, workspace=ws, timer=tm))
+        apply_us = 1e3 * float(np.median(tm.durations_ms()[: info.iterations]))
+        res[prec] = (x.clone(), info, ms, setup_ms, apply_us)
+    x64 = res["fp64"][0]
+    for prec in ("fp64", "fp32"):
+        x, info, ms, setup_ms, apply_us = res[prec]
+        err = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
+        elem = 4 if prec == "fp32" else 8
+        ab = elem * A_h.n * 33 // 2 + 56 * A_h.n
+        print(json.dumps({"mode": "precision", "workload": "powerlaw_4m", "precision": prec,
+                          "n": A_h.n, "nnz": A_h.nnz, "mean_nnz_row": round(float(deg.mean()), 2),
+                          "max_nnz_row": int(deg.max()), "block_size": 32,
+                          "pcg_iterations": info.iterations, "status": info.status,
+                          "rel_res_true": info.rel_res_true, "pcg_ms": round(ms, 3),
+                          "us_per_iteration": round(1e3 * ms / info.iterations, 2),
+                          "apply_us": round(apply_us, 2),
+                          "apply_gbps": round(ab / (apply_us * 1e-6) / 1e9, 1),
+                          "rel_err_vs_fp64_path": err, "setup_ms": round(setup_ms, 3),
+                          "gen_s": round(gen_s, 1)}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
               "(the solver runs on a single MI355X).", file=sys.stderr)
         sys.exit(2)
+    if args.mode != "headline":
+        {"nb_sweep": mode_nb_sweep, "batch": mode_batch, "adjoint": mode_adjoint,
+         "precision": mode_precision}[args.mode](args)
+        return
 
     import numpy as np
     import torch
@@ -99,7 +269,7 @@ def main():
     def step(timer=None):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
         ev[0].record()
-        M = bjp.precondition(A, block_size=W.block_size)
+        M = bjp.precondition(A, block_size=W.block_size, precision=args.precision)
         ev[1].record()
         x, info = bjp.pcg_solve(A, M, b, tol=W.tol, workspace=pcg_ws, timer=timer)
         ev[2].record()
@@ -161,7 +331,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f64+f32-block-inverses",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": W.A.n, "nnz": W.A.nnz,
                    "block_size": W.block_size, "tol": W.tol, "lanczos_steps": steps_k,

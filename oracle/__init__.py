@@ -19,6 +19,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "bjp_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# A test that plants a mistake in a copy of the oracle points this at the
+# mutant's build; it is never set by the product or the benchmark.
+_LIB_OVERRIDE = os.environ.get("BJP_ORACLE_LIB")
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOTSPD", -3: "ENOCONV", -4: "EBREAKDOWN", -5: "ENONFINITE"}
 
@@ -47,8 +50,11 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        build(force=False)
-        L = C.CDLL(_LIB)
+        if _LIB_OVERRIDE:
+            L = C.CDLL(_LIB_OVERRIDE)
+        else:
+            build(force=False)
+            L = C.CDLL(_LIB)
         L.orc_csr_validate.argtypes = [C.c_int, _i32p, _i32p, _f64p]
         L.orc_spmv.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, _f64p]
         L.orc_dot.argtypes = [C.c_int, _f64p, _f64p]
