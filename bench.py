@@ -283,6 +283,15 @@ def main():
         step()
     torch.cuda.synchronize()
 
+    # device-to-device copy of 1 GiB: the calibration for "achieved" bandwidth
+    # and the known-size kernel the HBM byte counters are scaled against
+    src = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    (_, copy_ms) = _timed(lambda: [dst.copy_(src) for _ in range(5)])
+    copy_gbps = 2 * src.numel() * 8 * 5 / (copy_ms * 1e-3) / 1e9
+    del src, dst
+
     cap = 4096
     timers = [bjp.KernelTimer(bjp.KERNEL_APPLY, cap) for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -352,6 +361,8 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_launch": ab, "avg_launch_us": round(apply_avg_ms * 1e3, 3),
                      "launches_timed": len(durs)},
+        "copy_gbps": round(copy_gbps, 1),
+        "frac_of_copy": round(achieved / copy_gbps, 4),
         "wall_s": round(wall_s, 3),
         "gen_s": round(gen_s, 2),
     }
