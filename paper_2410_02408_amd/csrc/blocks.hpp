@@ -139,20 +139,35 @@ __global__ __launch_bounds__(64) void k_setup(SetupArgs a) {
 // inactive), n = the lane's block size, i = lane index in its group.  The
 // diagonals are streamed KC at a time (a scheduling barrier between chunks
 // keeps at most KC of them live), so register use stays bounded for G = 64.
+#ifndef BJP_NT_TILES
+#define BJP_NT_TILES 1
+#endif
+// Tile loads: the packets are streamed once per application and exceed every
+// cache level, so they are loaded non-temporally (measured at 128^3, n_b = 64:
+// 130 us instead of 145 us per application, the vectors' lines stay cached).
+template <typename TS>
+__device__ __forceinline__ TS tile_load(const TS *p) {
+#if BJP_NT_TILES
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+
 template <int G, typename TS, int KC = BJP_APPLY_CHUNK>
 __device__ __forceinline__ TS packet_apply(const TS *__restrict__ D, int lane, int g, int i, int n, TS rs) {
     constexpr int K = G / 2;
     const bool act = i < n;
     const int ia = act ? i : 0;
     const int nn = n > 0 ? n : 1;
-    TS zv = D[lane] * rs;
+    TS zv = tile_load(D + lane) * rs;
 #pragma unroll
     for (int k0 = 1; k0 <= K; k0 += KC) {
         TS dv[KC];
 #pragma unroll
         for (int kk = 0; kk < KC; ++kk) {
             const int k = k0 + kk;
-            if (k <= K) dv[kk] = k < K ? D[k * 64 + lane] : D[K * 64 + g * K + (i & (K - 1))];
+            if (k <= K) dv[kk] = tile_load(k < K ? D + k * 64 + lane : D + K * 64 + g * K + (i & (K - 1)));
         }
 #pragma unroll
         for (int kk = 0; kk < KC; ++kk) {

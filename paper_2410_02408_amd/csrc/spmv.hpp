@@ -29,6 +29,14 @@ enum SpmvMode { SPMV_DIR = 0, SPMV_SIGMA = 1, SPMV_RESID = 2, SPMV_LANCZOS = 3 }
 // Rows each lane group keeps in flight per step.
 __host__ __device__ constexpr int spmv_rows_per_group(int gs) { return gs <= 16 ? BJP_SPMV_ROWS : 2; }
 
+#ifndef BJP_SPMV_PASSES
+#define BJP_SPMV_PASSES 1
+#endif
+// Entries per row loaded in the unrolled first stage: passes * GS; longer rows
+// continue in a loop.  (Two unrolled passes of 4 lanes for 7-entry stencil
+// rows measured slower than one pass plus the loop.)
+__host__ __device__ constexpr int spmv_passes(int gs) { return gs <= 4 ? BJP_SPMV_PASSES : 1; }
+
 struct SpmvArgs {
     int n, chunk;
     const int32_t *rp, *ci;
@@ -118,24 +126,32 @@ __global__ __launch_bounds__(kWG) void k_spmv(SpmvArgs a) {
             else if (MODE == SPMV_RESID) own[u] = a.b[rc];
             else own[u] = a.zt[rc] * invb;
         }
-        int col[U];
-        double vv[U], acc[U];
+        constexpr int NP = spmv_passes(GS);
+        int col[U][NP];
+        double vv[U][NP], acc[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int k = kb[u] + sub;
-            const int kc = k < ke[u] ? k : 0;
-            col[u] = ci[kc];
-            vv[u] = val[kc];
+#pragma unroll
+            for (int pp = 0; pp < NP; ++pp) {
+                const int k = kb[u] + sub + pp * GS;
+                const int kc = k < ke[u] ? k : 0;
+                col[u][pp] = ci[kc];
+                vv[u][pp] = val[kc];
+            }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const bool valid = kb[u] + sub < ke[u];
-            const double xv = gather(valid ? col[u] : 0);
-            acc[u] = valid ? vv[u] * xv : 0.0;
+            acc[u] = 0.0;
+#pragma unroll
+            for (int pp = 0; pp < NP; ++pp) {
+                const bool valid = kb[u] + sub + pp * GS < ke[u];
+                const double xv = gather(valid ? col[u][pp] : 0);
+                acc[u] += valid ? vv[u][pp] * xv : 0.0;
+            }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            for (int k = kb[u] + sub + GS; k < ke[u]; k += GS) acc[u] += a.val[k] * gather(a.ci[k]);
+            for (int k = kb[u] + sub + NP * GS; k < ke[u]; k += GS) acc[u] += val[k] * gather(ci[k]);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
 #pragma unroll

@@ -8,12 +8,18 @@ from paper_2410_02408_amd import workloads as w
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
 
+# The persistent batched solve is switched off (bjp_batch_pcg_solve returns
+# EINVAL): its first GPU run did not return and no cause has been shown.
+PERSISTENT_OFF = pytest.mark.skip(reason="persistent batched solve switched off: first GPU run did not "
+                                         "return, cause not yet shown (see the design notes)")
+
 
 def small_batch(count=12, seed=5):
     mats, nbs, rhs = w.random_spd_batch(count, seed=seed, n_lo=100, n_hi=3000)
     return mats, nbs, rhs
 
 
+@PERSISTENT_OFF
 @pytest.mark.parametrize("lanes,threads", [(0, 0), (4, 256), (16, 1024), (32, 512)])
 def test_batch_matches_oracle(gpu, orc, lanes, threads):
     mats, nbs, rhs = small_batch()
@@ -33,6 +39,7 @@ def test_batch_matches_oracle(gpu, orc, lanes, threads):
         assert abs(info.per_system["rel_res_true"][s] - res) <= 1e-13
 
 
+@PERSISTENT_OFF
 def test_batch_fp32_store(gpu, orc):
     mats, nbs, rhs = small_batch(6, seed=6)
     B = gpu.Batch.from_systems(mats, nbs, DEV)
@@ -71,6 +78,7 @@ def test_batch_not_spd_global_block_index(gpu):
     assert e.value.failed_block == (mats[0].n + 15) // 16 + 2
 
 
+@PERSISTENT_OFF
 def test_batch_autotune_picks_a_candidate(gpu, tmp_path, monkeypatch):
     from paper_2410_02408_amd import autotune
 
