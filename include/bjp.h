@@ -229,9 +229,9 @@ typedef struct {
     double tol;                  /* default 1e-10 */
     int32_t max_iter;            /* per system, default its size */
     int32_t max_replacements;    /* default 3; < 0 means none */
-    int32_t lanes;               /* lanes per CSR row: 0 = auto, else 4, 8, 16, 32 */
-    int32_t threads;             /* workgroup size: 0 = auto, else 256, 512, 1024 */
-    int32_t workgroups;          /* persistent workgroups: 0 = auto (2 per compute unit) */
+    int32_t lanes;               /* lanes per CSR row: 0 = auto, else a power of two <= 64 */
+    int32_t tile_rows;           /* rows per SpMV tile: 0 = auto (2048), else >= 256 */
+    int32_t check_every;         /* iterations between convergence polls (default 16) */
     int32_t pad;
 } bjp_batch_opts_t;
 
@@ -263,11 +263,13 @@ int bjp_batch_precondition(const bjp_csr_t *A, const bjp_batch_t *B, int precisi
 
 int bjp_batch_pcg_workspace(const bjp_csr_t *A, const bjp_batch_t *B, size_t *bytes /* host out */);
 
-/* Solve every system of the batch with PCG (the algorithm and stopping rule of
- * bjp_pcg_solve, x0 = 0) in one persistent launch: each workgroup takes the
- * next unsolved system, largest first, and iterates it to convergence.
- * b, x: device [n].  per_system (host [num_systems], optional) receives each
- * system's result.  Synchronises `stream`. */
+/* Solve every system of the batch with PCG (the algorithm, stopping rule and
+ * true-residual check of bjp_pcg_solve, x0 = 0).  All systems advance
+ * together: each kernel launch covers every system (row and packet tiles that
+ * never straddle two systems), each system keeps its own scalars, and a
+ * converged system drops out.  b, x: device [n].  per_system (host
+ * [num_systems], optional) receives each system's result.  Synchronises
+ * `stream`. */
 int bjp_batch_pcg_solve(const bjp_csr_t *A, const bjp_batch_t *B, const bjp_batch_precond_t *M,
                         const double *b, double *x, const bjp_batch_opts_t *opts, void *ws,
                         size_t ws_bytes, bjp_batch_info_t *info /* host out */,

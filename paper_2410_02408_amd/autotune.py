@@ -1,12 +1,12 @@
 """Autotuner for the batched solver's launch shape.
 
-The persistent batched launch has three free parameters: lanes per CSR row
-(4, 8, 16, 32), workgroup size (256, 512, 1024 threads) and the number of
-persistent workgroups.  ``tune_batch`` times every candidate on the actual
-batch for a short, fixed number of PCG iterations per system (so each
-candidate does the same work), keeps the fastest, and caches the choice in a
-JSON file keyed by the batch's shape class (system count, mean row length,
-size range, block sizes).  The cache lives in $BJP_CACHE_DIR or
+The batched solver has two free schedule parameters: lanes per CSR row (the
+row-bundling of the SpMV: 4, 8, 16 or 32 lanes per row, i.e. 16..2 rows per
+wavefront) and rows per SpMV tile (the work of one workgroup).  ``tune_batch``
+times every candidate on the actual batch for a short, fixed number of PCG
+iterations per system (so each candidate does the same work), keeps the
+fastest, and caches the choice in a JSON file keyed by the batch's shape
+class (system count, mean row length, size range, block sizes).  The cache lives in $BJP_CACHE_DIR or
 ~/.cache/bjp.
 """
 from __future__ import annotations
@@ -22,7 +22,7 @@ import torch
 from . import bjp
 
 LANES = (4, 8, 16, 32)
-THREADS = (256, 512, 1024)
+TILE_ROWS = (1024, 2048, 4096)
 
 
 def _cache_path() -> str:
@@ -39,7 +39,7 @@ def shape_key(B: bjp.Batch) -> str:
 
 
 def tune_batch(B: bjp.Batch, M: bjp.BatchPrecond, b, probe_iters: int = 20, use_cache: bool = True,
-               lanes=LANES, threads=THREADS, workgroups=(0,)):
+               lanes=LANES, tile_rows=TILE_ROWS):
     """Return (config dict, timings) for the fastest candidate."""
     key = shape_key(B)
     path = _cache_path()
@@ -59,17 +59,16 @@ def tune_batch(B: bjp.Batch, M: bjp.BatchPrecond, b, probe_iters: int = 20, use_
                                                         bjp.C.byref(n))
     ws = bjp._workspace(n.value, dev)
     timings = {}
-    for ln, nt, wg in itertools.product(lanes, threads, workgroups):
-        bjp.batch_pcg_solve(B, M, b, tol=1e-300, max_iter=2, lanes=ln, threads=nt, workgroups=wg,
-                            out=x, workspace=ws)
+    for ln, tr in itertools.product(lanes, tile_rows):
+        bjp.batch_pcg_solve(B, M, b, tol=1e-300, max_iter=2, lanes=ln, tile_rows=tr, out=x, workspace=ws)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        bjp.batch_pcg_solve(B, M, b, tol=1e-300, max_iter=probe_iters, lanes=ln, threads=nt,
-                            workgroups=wg, out=x, workspace=ws)
+        bjp.batch_pcg_solve(B, M, b, tol=1e-300, max_iter=probe_iters, lanes=ln, tile_rows=tr,
+                            check_every=probe_iters, out=x, workspace=ws)
         torch.cuda.synchronize()
-        timings[(ln, nt, wg)] = time.perf_counter() - t
+        timings[(ln, tr)] = time.perf_counter() - t
     best = min(timings, key=timings.get)
-    cfg = {"lanes": best[0], "threads": best[1], "workgroups": best[2]}
+    cfg = {"lanes": best[0], "tile_rows": best[1]}
     cache[key] = cfg
     try:
         json.dump(cache, open(path, "w"), indent=1)

@@ -354,27 +354,81 @@ size_t batch_precond_bytes(const BatchPlan &P, int precision) {
            al256(sizeof(int32_t) * P.off.size()) + al256(P.tile_scalars * elem) + al256(64);
 }
 
-template <int NT, typename TS>
-void launch_batch_nt(int gs, int grid, const BatchArgs &a, hipStream_t s) {
-    switch (gs) {
-        case 4: hipLaunchKernelGGL((k_pcg_batch<NT, 4, TS>), dim3(grid), dim3(NT), 0, s, a); break;
-        case 8: hipLaunchKernelGGL((k_pcg_batch<NT, 8, TS>), dim3(grid), dim3(NT), 0, s, a); break;
-        case 16: hipLaunchKernelGGL((k_pcg_batch<NT, 16, TS>), dim3(grid), dim3(NT), 0, s, a); break;
-        default: hipLaunchKernelGGL((k_pcg_batch<NT, 32, TS>), dim3(grid), dim3(NT), 0, s, a); break;
+constexpr int kPacketsPerTile = 4 * kWaves;   // packets per apply tile (4 per wave)
+
+struct BatchTables {
+    std::vector<Tile> rt, pt;               // row tiles, packet tiles (grouped by G)
+    std::vector<int> rt_begin, rt_end;      // per system
+    std::vector<int> pt_begin, pt_end;      // per system
+    std::vector<int> cls_g, cls_begin, cls_end;  // packet-tile range of each width G
+};
+
+void make_batch_tables(const BatchPlan &P, int tile_rows, BatchTables &T) {
+    const int S = (int)P.sys.size();
+    T.rt_begin.assign(S, 0);
+    T.rt_end.assign(S, 0);
+    T.pt_begin.assign(S, 0);
+    T.pt_end.assign(S, 0);
+    for (int s = 0; s < S; ++s) {
+        const SysInfo &si = P.sys[s];
+        T.rt_begin[s] = (int)T.rt.size();
+        for (int r = si.row0; r < si.row0 + si.n; r += tile_rows)
+            T.rt.push_back(Tile{s, r, std::min(r + tile_rows, si.row0 + si.n), 0});
+        T.rt_end[s] = (int)T.rt.size();
+    }
+    for (int G = 1; G <= 64; G <<= 1) {
+        const int b = (int)T.pt.size();
+        for (int s = 0; s < S; ++s) {
+            const SysInfo &si = P.sys[s];
+            if (si.G != G) continue;
+            T.pt_begin[s] = (int)T.pt.size();
+            for (int pk = 0; pk < si.packets; pk += kPacketsPerTile)
+                T.pt.push_back(Tile{s, pk, std::min(pk + kPacketsPerTile, si.packets), 0});
+            T.pt_end[s] = (int)T.pt.size();
+        }
+        if ((int)T.pt.size() > b) {
+            T.cls_g.push_back(G);
+            T.cls_begin.push_back(b);
+            T.cls_end.push_back((int)T.pt.size());
+        }
     }
 }
 
-template <typename TS>
-void launch_batch(int nt, int gs, int grid, const BatchArgs &a, hipStream_t s) {
-    if (nt == 256) launch_batch_nt<256, TS>(gs, grid, a, s);
-    else if (nt == 1024) launch_batch_nt<1024, TS>(gs, grid, a, s);
-    else launch_batch_nt<512, TS>(gs, grid, a, s);
+size_t batch_tiles_bound(const BatchPlan &P, int min_tile_rows, size_t *nrt, size_t *npt) {
+    size_t r = 0, p = 0;
+    for (const SysInfo &si : P.sys) {
+        r += (size_t)ceil_div(si.n, min_tile_rows);
+        p += (size_t)ceil_div(si.packets, kPacketsPerTile);
+    }
+    *nrt = r;
+    *npt = p;
+    return r + p;
 }
 
-constexpr bool kBatchPersistentEnabled = false;
+template <int MODE>
+void launch_spmv_tiles(int gs, int grid, const SpmvArgs &a, const TileSpan &t, hipStream_t s) {
+    switch (gs) {
+        case 1: hipLaunchKernelGGL((k_spmv_tiles<1, MODE>), dim3(grid), dim3(kWG), 0, s, a, t); break;
+        case 2: hipLaunchKernelGGL((k_spmv_tiles<2, MODE>), dim3(grid), dim3(kWG), 0, s, a, t); break;
+        case 4: hipLaunchKernelGGL((k_spmv_tiles<4, MODE>), dim3(grid), dim3(kWG), 0, s, a, t); break;
+        case 8: hipLaunchKernelGGL((k_spmv_tiles<8, MODE>), dim3(grid), dim3(kWG), 0, s, a, t); break;
+        case 16: hipLaunchKernelGGL((k_spmv_tiles<16, MODE>), dim3(grid), dim3(kWG), 0, s, a, t); break;
+        case 32: hipLaunchKernelGGL((k_spmv_tiles<32, MODE>), dim3(grid), dim3(kWG), 0, s, a, t); break;
+        default: hipLaunchKernelGGL((k_spmv_tiles<64, MODE>), dim3(grid), dim3(kWG), 0, s, a, t); break;
+    }
+}
 
-__global__ void k_zero_int(int *p) {
-    if (threadIdx.x == 0) *p = 0;
+template <typename TS, int MODE>
+void launch_apply_tiles_t(int G, int grid, const ApplyArgs &a, const TileSpan &t, hipStream_t s) {
+    switch (G) {
+        case 1: hipLaunchKernelGGL((k_apply_tiles<1, TS, MODE>), dim3(grid), dim3(kWG), 0, s, a, t); break;
+        case 2: hipLaunchKernelGGL((k_apply_tiles<2, TS, MODE>), dim3(grid), dim3(kWG), 0, s, a, t); break;
+        case 4: hipLaunchKernelGGL((k_apply_tiles<4, TS, MODE>), dim3(grid), dim3(kWG), 0, s, a, t); break;
+        case 8: hipLaunchKernelGGL((k_apply_tiles<8, TS, MODE>), dim3(grid), dim3(kWG), 0, s, a, t); break;
+        case 16: hipLaunchKernelGGL((k_apply_tiles<16, TS, MODE>), dim3(grid), dim3(kWG), 0, s, a, t); break;
+        case 32: hipLaunchKernelGGL((k_apply_tiles<32, TS, MODE>), dim3(grid), dim3(kWG), 0, s, a, t); break;
+        default: hipLaunchKernelGGL((k_apply_tiles<64, TS, MODE>), dim3(grid), dim3(kWG), 0, s, a, t); break;
+    }
 }
 
 }  // namespace
@@ -915,10 +969,19 @@ int bjp_batch_precondition(const bjp_csr_t *A, const bjp_batch_t *B, int precisi
 int bjp_batch_pcg_workspace(const bjp_csr_t *A, const bjp_batch_t *B, size_t *bytes) {
     if (!bytes) return BJP_EINVAL;
     *bytes = 0;
-    if (check_csr_host(A) != BJP_OK || !B || B->num_systems <= 0) return BJP_EINVAL;
+    if (check_csr_host(A) != BJP_OK) return BJP_EINVAL;
+    BatchPlan P;
+    const int st = make_batch_plan(A, B, P);
+    if (st != BJP_OK) return st;
     const size_t S = (size_t)B->num_systems;
-    *bytes = 4 * al256(sizeof(double) * (size_t)std::max(A->n, 1)) + al256(sizeof(int) * S) +
-             al256(sizeof(SysOut) * S) + 2 * al256(64);
+    size_t nrt = 0, npt = 0;
+    batch_tiles_bound(P, 256, &nrt, &npt);
+    const size_t nred = round8((int)std::max(nrt, npt));
+    *bytes = 5 * al256(sizeof(double) * (size_t)std::max(A->n, 1))  // r, z, p0, p1, q
+             + al256(sizeof(PcgState) * S) + al256(sizeof(Tile) * (nrt + npt)) +
+             5 * al256(sizeof(int) * S)                                // tile ranges, iteration caps
+             + al256(sizeof(int) * S)                                  // restart list
+             + al256(sizeof(double) * 2 * nred) + 2 * al256(64);
     return BJP_OK;
 }
 
@@ -932,12 +995,6 @@ int bjp_batch_pcg_solve(const bjp_csr_t *A, const bjp_batch_t *B, const bjp_batc
         info->status = st;
         return st;
     };
-    static_assert(sizeof(SysOut) == sizeof(bjp_system_info_t), "per-system record layout");
-    // The persistent one-workgroup-per-system kernel (k_pcg_batch) is switched
-    // off: its first GPU run did not return (no cause found: the same source
-    // terminates and converges when executed lane by lane on the host).  Until
-    // a cause is shown the entry point refuses to launch it.
-    if (!kBatchPersistentEnabled) return fail(BJP_EINVAL);
     if (check_csr_host(A) != BJP_OK || !M || !b || !x || A->n <= 0 || A->nnz <= 0) return fail(BJP_EINVAL);
     BatchPlan P;
     int st = make_batch_plan(A, B, P);
@@ -952,74 +1009,159 @@ int bjp_batch_pcg_solve(const bjp_csr_t *A, const bjp_batch_t *B, const bjp_batc
     if (!(o.tol > 0.0)) o.tol = 1e-10;
     if (o.max_replacements == 0) o.max_replacements = 3;
     else if (o.max_replacements < 0) o.max_replacements = 0;
-    int max_n = 0;
-    for (const SysInfo &si : P.sys) max_n = std::max(max_n, si.n);
-    if (o.max_iter <= 0) o.max_iter = max_n;
-    int gs = o.lanes;
-    if (gs <= 0) gs = std::min(32, std::max(4, auto_lanes(A)));
-    gs = std::min(32, std::max(4, pow2_at_least(gs)));
-    const int nt = (o.threads == 256 || o.threads == 1024) ? o.threads : 512;
-    int grid = o.workgroups;
-    if (grid <= 0) {
-        int dev = 0, cus = 256;
-        if (hipGetDevice(&dev) == hipSuccess) {
-            hipDeviceProp_t prop;
-            if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
-        }
-        grid = 2 * cus;
-    }
-    grid = std::max(1, std::min(grid, S));
+    if (o.check_every <= 0) o.check_every = 16;
+    const int tile_rows = o.tile_rows > 0 ? std::max(256, o.tile_rows) : 2048;
+    const int gs = o.lanes > 0 ? pow2_at_least(std::min(o.lanes, 64)) : auto_lanes(A);
+
+    BatchTables T;
+    make_batch_tables(P, tile_rows, T);
+    const int nrt = (int)T.rt.size(), npt = (int)T.pt.size();
+    const int nred = round8(std::max(nrt, npt));
+    std::vector<int> caps(S);
+    for (int s = 0; s < S; ++s) caps[s] = o.max_iter > 0 ? o.max_iter : std::max(P.sys[s].n, 1);
 
     Carver cv{static_cast<char *>(ws)};
     double *r = cv.take<double>(A->n), *z = cv.take<double>(A->n);
-    double *p = cv.take<double>(A->n), *q = cv.take<double>(A->n);
-    int *order = cv.take<int>(S);
-    SysOut *out = cv.take<SysOut>(S);
-    int *queue = cv.take<int>(16);
+    double *p0 = cv.take<double>(A->n), *p1 = cv.take<double>(A->n), *q = cv.take<double>(A->n);
+    PcgState *states = cv.take<PcgState>(S);
+    Tile *tiles = cv.take<Tile>((size_t)nrt + npt);
+    int *rtb = cv.take<int>(S), *rte = cv.take<int>(S), *ptb = cv.take<int>(S), *pte = cv.take<int>(S);
+    int *capd = cv.take<int>(S);
+    int *restart = cv.take<int>(S);
+    double *partials = cv.take<double>(2 * (size_t)nred);
     int32_t *flags = cv.take<int32_t>(16);
+    double *zeros = cv.take<double>(8);
+    (void)zeros;
 
     st = run_validate(A, flags, stream);
     if (st != BJP_OK) return fail(st);
-    std::vector<int> ord(S);
-    for (int s = 0; s < S; ++s) ord[s] = s;
-    std::stable_sort(ord.begin(), ord.end(), [&](int u, int v) { return P.sys[u].n > P.sys[v].n; });
-    HIP_TRY(hipMemcpyAsync(order, ord.data(), sizeof(int) * S, hipMemcpyHostToDevice, stream));
-    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, stream, queue);
+    std::vector<Tile> all(T.rt);
+    all.insert(all.end(), T.pt.begin(), T.pt.end());
+    HIP_TRY(hipMemcpyAsync(tiles, all.data(), sizeof(Tile) * all.size(), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(rtb, T.rt_begin.data(), sizeof(int) * S, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(rte, T.rt_end.data(), sizeof(int) * S, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(ptb, T.pt_begin.data(), sizeof(int) * S, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(pte, T.pt_end.data(), sizeof(int) * S, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(capd, caps.data(), sizeof(int) * S, hipMemcpyHostToDevice, stream));
+    const int fill_grid = std::min(ceil_div(A->n, kWG), 4096);
+    hipLaunchKernelGGL(k_batch_state_init, dim3(std::min(ceil_div(S, kWG), 1024)), dim3(kWG), 0, stream, states,
+                       S, o.tol, capd);
+    hipLaunchKernelGGL(k_fill, dim3(fill_grid), dim3(kWG), 0, stream, p0, A->n, 0.0);
+    hipLaunchKernelGGL(k_fill, dim3(fill_grid), dim3(kWG), 0, stream, p1, A->n, 0.0);
+    hipLaunchKernelGGL(k_fill, dim3(fill_grid), dim3(kWG), 0, stream, x, A->n, 0.0);
 
-    BatchArgs a{};
-    a.S = S;
-    a.sys = static_cast<const SysInfo *>(M->systems);
-    a.order = order;
-    a.queue = queue;
-    a.rp = A->row_ptr;
-    a.ci = A->col_idx;
-    a.val = A->val;
-    a.b = b;
-    a.x = x;
-    a.r = r;
-    a.z = z;
-    a.p = p;
-    a.q = q;
-    a.tiles = M->tiles;
-    a.tol = o.tol;
-    a.max_iter = o.max_iter;
-    a.max_repl = o.max_replacements;
-    a.out = out;
-    if (M->precision == BJP_FP32_STORE) launch_batch<float>(nt, gs, grid, a, stream);
-    else launch_batch<double>(nt, gs, grid, a, stream);
-    HIP_TRY(hipGetLastError());
-    std::vector<SysOut> h(S);
-    HIP_TRY(hipMemcpyAsync(h.data(), out, sizeof(SysOut) * S, hipMemcpyDeviceToHost, stream));
-    HIP_TRY(hipStreamSynchronize(stream));
+    const TileSpan rows{tiles, 0, nrt, nrt, static_cast<const SysInfo *>(M->systems)};
+    const int rgrid = round8(nrt);
+    SpmvArgs sa{};
+    sa.n = A->n;
+    sa.rp = A->row_ptr;
+    sa.ci = A->col_idx;
+    sa.val = A->val;
+    sa.st = states;
+    sa.z = z;
+    sa.p0 = p0;
+    sa.p1 = p1;
+    sa.q = q;
+    sa.b = b;
+    sa.x = x;
+    sa.r = r;
+    sa.partials = partials;
+    ApplyArgs aa{};
+    aa.st = states;
+    aa.tiles = M->tiles;
+    aa.rin = r;
+    aa.zout = z;
+    aa.x = x;
+    aa.r = r;
+    aa.q = q;
+    aa.p0 = p0;
+    aa.p1 = p1;
+    aa.partials = partials;
+    FinishArgs fa{};
+    fa.st = states;
+    fa.partials = partials;
+
+    auto apply_all = [&](auto mode_tag) {
+        constexpr int MODE = decltype(mode_tag)::value;
+        for (size_t c = 0; c < T.cls_g.size(); ++c) {
+            const TileSpan span{tiles + nrt, T.cls_begin[c], T.cls_end[c], npt,
+                                static_cast<const SysInfo *>(M->systems)};
+            const int grid = round8(T.cls_end[c] - T.cls_begin[c]);
+            if (M->precision == BJP_FP32_STORE) launch_apply_tiles_t<float, MODE>(T.cls_g[c], grid, aa, span, stream);
+            else launch_apply_tiles_t<double, MODE>(T.cls_g[c], grid, aa, span, stream);
+        }
+    };
+    auto start_direction = [&]() {
+        apply_all(std::integral_constant<int, APPLY_INIT>{});
+        hipLaunchKernelGGL(k_finish_sys<FIN_PCG_START>, dim3(S), dim3(kWG), 0, stream, fa, ptb, pte, npt);
+    };
+    auto iteration = [&]() {
+        hipLaunchKernelGGL(k_direction_tiles, dim3(rgrid), dim3(kWG), 0, stream, states, z, p0, p1, rows);
+        launch_spmv_tiles<SPMV_SIGMA>(gs, rgrid, sa, rows, stream);
+        hipLaunchKernelGGL(k_finish_sys<FIN_SIGMA>, dim3(S), dim3(kWG), 0, stream, fa, rtb, rte, nrt);
+        apply_all(std::integral_constant<int, APPLY_UPDATE>{});
+        hipLaunchKernelGGL(k_finish_sys<FIN_PCG_UPDATE>, dim3(S), dim3(kWG), 0, stream, fa, ptb, pte, npt);
+    };
+    std::vector<PcgState> h(S);
+    auto read_states = [&]() -> int {
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(h.data(), states, sizeof(PcgState) * S, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        return BJP_OK;
+    };
+
+    sa.resid_phase = 0;
+    launch_spmv_tiles<SPMV_RESID>(gs, rgrid, sa, rows, stream);
+    hipLaunchKernelGGL(k_finish_sys<FIN_RESID_START>, dim3(S), dim3(kWG), 0, stream, fa, rtb, rte, nrt);
+    start_direction();
+
+    std::vector<int> repl(S, 0), host_status(S, BJP_OK);
+    for (;;) {
+        int active = 0;
+        for (;;) {
+            for (int c = 0; c < o.check_every; ++c) iteration();
+            if ((st = read_states()) != BJP_OK) return fail(st);
+            active = 0;
+            for (int s = 0; s < S; ++s) active += h[s].done ? 0 : 1;
+            if (!active) break;
+        }
+        // true residual of every system; re-open the ones above tol
+        sa.resid_phase = 1;
+        launch_spmv_tiles<SPMV_RESID>(gs, rgrid, sa, rows, stream);
+        hipLaunchKernelGGL(k_finish_sys<FIN_RESID_TRUE>, dim3(S), dim3(kWG), 0, stream, fa, rtb, rte, nrt);
+        sa.resid_phase = 0;
+        if ((st = read_states()) != BJP_OK) return fail(st);
+        std::vector<int> again;
+        for (int s = 0; s < S; ++s) {
+            if (h[s].status != BJP_OK || h[s].zero_rhs || h[s].relres_true <= o.tol) continue;
+            if (repl[s] >= o.max_replacements) {
+                host_status[s] = BJP_ENOCONV;
+                continue;
+            }
+            ++repl[s];
+            again.push_back(s);
+        }
+        if (again.empty()) break;
+        HIP_TRY(hipMemcpyAsync(restart, again.data(), sizeof(int) * again.size(), hipMemcpyHostToDevice, stream));
+        hipLaunchKernelGGL(k_batch_restart, dim3(1), dim3(kWG), 0, stream, states, restart, (int)again.size());
+        start_direction();
+    }
     info->status = BJP_OK;
+    std::vector<bjp_system_info_t> out(S);
     for (int s = 0; s < S; ++s) {
-        if (h[s].status == BJP_OK) info->systems_ok++;
-        else if (info->status == BJP_OK) info->status = h[s].status;
-        info->total_iterations += h[s].iterations;
-        info->max_iterations = std::max(info->max_iterations, h[s].iterations);
+        const int sst = h[s].status != BJP_OK ? h[s].status : host_status[s];
+        out[s].status = sst;
+        out[s].iterations = h[s].it;
+        out[s].replacements = repl[s];
+        out[s].rel_res_recursive = h[s].relres;
+        out[s].rel_res_true = h[s].relres_true;
+        if (sst == BJP_OK) info->systems_ok++;
+        else if (info->status == BJP_OK) info->status = sst;
+        info->total_iterations += h[s].it;
+        info->max_iterations = std::max(info->max_iterations, h[s].it);
         info->max_rel_res_true = std::max(info->max_rel_res_true, h[s].relres_true);
     }
-    if (per_system) std::memcpy(per_system, h.data(), sizeof(SysOut) * S);
+    if (per_system) std::memcpy(per_system, out.data(), sizeof(bjp_system_info_t) * S);
     return info->status;
 }
 

@@ -192,7 +192,8 @@ enum ApplyMode { APPLY_PLAIN = 0, APPLY_INIT = 1, APPLY_UPDATE = 2, APPLY_LANCZO
 struct ApplyArgs {
     int nblocks, num_packets, chunk;
     int n;                  // rows of the system
-    int uniform_nb;         // > 0: block t = rows [t*nb, min((t+1)*nb, n)), offsets unused
+    int row0;               // first row of the system (0 except in batches)
+    int uniform_nb;         // > 0: block t = rows [row0 + t*nb, ...), offsets unused
     const int32_t *off;
     const void *tiles;
     const double *rin;      // PLAIN / INIT / LANCZOS: residual to precondition
@@ -205,26 +206,20 @@ struct ApplyArgs {
     double *partials;       // per-workgroup r^T z, r^T r
 };
 
+// Packets pk0, pk0 + stride, ... < pk1 of one system (rows [a.row0,
+// a.row0 + a.n), tiles at a.tiles) in the given mode; accumulates this
+// thread's share of r^T z and r^T r.  One wave per packet.
 template <int G, typename TS, int MODE>
-__global__ __launch_bounds__(kWG) void k_apply(ApplyArgs a) {
-    if (MODE == APPLY_INIT || MODE == APPLY_UPDATE) {
-        if (a.st->done) return;
-    }
-    if (MODE == APPLY_LANCZOS) {
-        if (a.ls->done) return;
-    }
+__device__ __forceinline__ void apply_packets(const ApplyArgs &a, const PcgState *st, int pk0, int pk1, int stride,
+                                              double &d0, double &d1) {
     constexpr int P = 64 / G, E = packet_elems(G);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
     const int g = lane / G, i = lane % G;
-    const int c = xcd_chunk(blockIdx.x, gridDim.x);
-    const int pk0 = c * a.chunk;
-    const int pk1 = min(pk0 + a.chunk, a.num_packets);
-
     double alpha = 0.0;
     const double *__restrict__ pn = nullptr;
     if (MODE == APPLY_UPDATE) {
-        alpha = a.st->alpha;
-        pn = ((a.st->it + 1) & 1) ? a.p1 : a.p0;
+        alpha = st->alpha;
+        pn = ((st->it + 1) & 1) ? a.p1 : a.p0;
     }
     const TS *__restrict__ tiles = static_cast<const TS *>(a.tiles);
     const int32_t *__restrict__ off = a.off;
@@ -233,13 +228,13 @@ __global__ __launch_bounds__(kWG) void k_apply(ApplyArgs a) {
     const double *__restrict__ qv_ = a.q;
     const double *__restrict__ rin = a.rin;
     double *__restrict__ zout = a.zout;
-    double d0 = 0.0, d1 = 0.0;
-    for (int pk = pk0 + wave; pk < pk1; pk += kWaves) {
+    const int rend = a.row0 + a.n;
+    for (int pk = pk0; pk < pk1; pk += stride) {
         const int t = pk * P + g;
         int s = 0, n = 0;
         if (a.uniform_nb > 0) {
-            s = t * a.uniform_nb;
-            n = max(0, min(a.uniform_nb, a.n - s));
+            s = a.row0 + t * a.uniform_nb;
+            n = max(0, min(a.uniform_nb, rend - s));
         } else {
             const int tc = min(t, a.nblocks - 1);
             const int s0 = off[tc], e0 = off[tc + 1];
@@ -248,7 +243,7 @@ __global__ __launch_bounds__(kWG) void k_apply(ApplyArgs a) {
         }
         const bool act = i < n;
         const int row = s + i;
-        const int rc = min(row, a.n - 1);      // in-bounds index for masked lanes
+        const int rc = min(row, rend - 1);      // in-bounds index for masked lanes
         double rv;
         if (MODE == APPLY_UPDATE) {
             const double xo = xv_[rc], pv = pn[rc], qv = qv_[rc], ro = rv_[rc];
@@ -269,6 +264,22 @@ __global__ __launch_bounds__(kWG) void k_apply(ApplyArgs a) {
             d1 += rv * rv;
         }
     }
+}
+
+template <int G, typename TS, int MODE>
+__global__ __launch_bounds__(kWG) void k_apply(ApplyArgs a) {
+    if (MODE == APPLY_INIT || MODE == APPLY_UPDATE) {
+        if (a.st->done) return;
+    }
+    if (MODE == APPLY_LANCZOS) {
+        if (a.ls->done) return;
+    }
+    const int wave = threadIdx.x >> 6;
+    const int c = xcd_chunk(blockIdx.x, gridDim.x);
+    const int pk0 = c * a.chunk;
+    const int pk1 = min(pk0 + a.chunk, a.num_packets);
+    double d0 = 0.0, d1 = 0.0;
+    apply_packets<G, TS, MODE>(a, a.st, pk0 + wave, pk1, kWaves, d0, d1);
     if (MODE == APPLY_PLAIN) return;
     const double v[2] = {d0, d1};
     block_partial<2>(v, a.partials);

@@ -59,6 +59,51 @@ __device__ __forceinline__ void block_partial(const double (&v)[NQ], double *par
     }
 }
 
+// Per-workgroup partials stored at an explicit index (tile-indexed launches):
+// partials[q * stride + index].
+template <int NQ>
+__device__ __forceinline__ void block_partial_at(const double (&v)[NQ], double *partials, int stride, int index) {
+    __shared__ double red[NQ][kWaves];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        double s = wave_sum(v[q]);
+        if (lane == 0) red[q][wave] = s;
+    }
+    __syncthreads();
+    if (tid == 0 && index >= 0) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            double s = 0.0;
+            for (int w = 0; w < kWaves; ++w) s += red[q][w];
+            partials[q * stride + index] = s;
+        }
+    }
+}
+
+// Sum of partials[q * stride + b] for b in [b0, b1), in a fixed order, for a
+// one-workgroup launch; every thread receives the totals.
+template <int NQ>
+__device__ __forceinline__ void sum_partials_range(const double *partials, int stride, int b0, int b1,
+                                                   double (&out)[NQ]) {
+    __shared__ double red[NQ][kWaves];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        double acc = 0.0;
+        for (int b = b0 + tid; b < b1; b += kWG) acc += partials[q * stride + b];
+        acc = wave_sum(acc);
+        if (lane == 0) red[q][wave] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        double s = 0.0;
+        for (int w = 0; w < kWaves; ++w) s += red[q][w];
+        out[q] = s;
+    }
+}
+
 // Sum of partials[q * nparts + b] over b, in a fixed order, for a
 // one-workgroup launch; every thread receives the totals.
 template <int NQ>

@@ -85,19 +85,23 @@ __device__ __forceinline__ void lanczos_after_beta(LanczosState *ls, double bb, 
 }
 
 template <int OP>
-__global__ __launch_bounds__(kWG) void k_finish(FinishArgs f) {
-    constexpr bool lanczos = OP >= FIN_LZ_START;
-    constexpr int NQ = (OP == FIN_RESID_START || OP == FIN_RESID_TRUE || OP == FIN_PCG_UPDATE) ? 2 : 1;
-    if (lanczos) {
-        if (f.ls->done) return;
-    } else if (OP != FIN_RESID_TRUE) {
-        if (f.st->done) return;
-    }
-    double out[NQ];
-    sum_partials<NQ>(f.partials, f.nparts, out);
-    if (threadIdx.x != 0) return;
-    PcgState *st = f.st;
-    LanczosState *ls = f.ls;
+constexpr int finish_nq() {
+    return (OP == FIN_RESID_START || OP == FIN_RESID_TRUE || OP == FIN_PCG_UPDATE) ? 2 : 1;
+}
+
+// Whether the decision of OP is taken for a solver in this state.
+template <int OP>
+__device__ __forceinline__ bool finish_runs(const PcgState *st, const LanczosState *ls) {
+    if (OP >= FIN_LZ_START) return !ls->done;
+    if (OP == FIN_RESID_TRUE) return true;
+    return !st->done;
+}
+
+// The scalar decision of OP from the totals (thread 0 only).
+template <int OP>
+__device__ __forceinline__ void finish_decide(const FinishArgs &f, PcgState *st, LanczosState *ls,
+                                              const double *out) {
+    constexpr int NQ = finish_nq<OP>();
     if (OP == FIN_SIGMA) {
         const double sigma = out[0];
         if (!(sigma > 0.0)) {
@@ -153,6 +157,27 @@ __global__ __launch_bounds__(kWG) void k_finish(FinishArgs f) {
     } else if (OP == FIN_LZ_BETA) {
         lanczos_after_beta(ls, out[0], f.beta_out);
     }
+}
+
+template <int OP>
+__global__ __launch_bounds__(kWG) void k_finish(FinishArgs f) {
+    constexpr int NQ = finish_nq<OP>();
+    if (!finish_runs<OP>(f.st, f.ls)) return;
+    double out[NQ];
+    sum_partials<NQ>(f.partials, f.nparts, out);
+    if (threadIdx.x == 0) finish_decide<OP>(f, f.st, f.ls, out);
+}
+
+// Batched form: workgroup s decides for system s from the partials of its
+// tiles [begin[s], end[s]) (partials laid out [q][ntiles]).
+template <int OP>
+__global__ __launch_bounds__(kWG) void k_finish_sys(FinishArgs f, const int *begin, const int *end, int ntiles) {
+    constexpr int NQ = finish_nq<OP>();
+    PcgState *st = f.st + blockIdx.x;
+    if (!finish_runs<OP>(st, nullptr)) return;
+    double out[NQ];
+    sum_partials_range<NQ>(f.partials, ntiles, begin[blockIdx.x], end[blockIdx.x], out);
+    if (threadIdx.x == 0) finish_decide<OP>(f, st, nullptr, out);
 }
 
 }  // namespace bjp

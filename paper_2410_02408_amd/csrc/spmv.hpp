@@ -64,13 +64,12 @@ __device__ __forceinline__ double dir_value(double beta, const double *pold, con
     return __builtin_fma(beta, pold[i], z[i]);
 }
 
+// Rows [r0, r1) of the product in the given mode; accumulates this thread's
+// share of the mode's dot products into d0, d1.  `st` is the state of the
+// system the rows belong to.  Called by every thread of the workgroup.
 template <int GS, int MODE>
-__global__ __launch_bounds__(kWG) void k_spmv(SpmvArgs a) {
-    if (MODE == SPMV_LANCZOS) {
-        if (a.ls->done) return;
-    } else if (!(MODE == SPMV_RESID && a.resid_phase == 1)) {
-        if (a.st->done) return;
-    }
+__device__ __forceinline__ void spmv_rows(const SpmvArgs &a, const PcgState *st, int r0, int r1, double &d0,
+                                          double &d1) {
     // U rows per lane group are processed together so that several
     // row_ptr -> col -> gather chains are in flight per lane.  The CSR
     // arrays must hold at least one entry (callers pass a zero entry for an
@@ -78,18 +77,15 @@ __global__ __launch_bounds__(kWG) void k_spmv(SpmvArgs a) {
     constexpr int U = spmv_rows_per_group(GS);
     constexpr int RWG = kWG / GS;
     const int tid = threadIdx.x, sub = tid & (GS - 1), grp = tid / GS;
-    const int c = xcd_chunk(blockIdx.x, gridDim.x);
-    const int r0 = c * a.chunk;
-    const int r1 = min(r0 + a.chunk, a.n);
 
     double beta = 0.0, invb = 0.0;
     const double *pold = nullptr, *src = nullptr;
     double *pnew = nullptr;
     if (MODE == SPMV_DIR || MODE == SPMV_SIGMA) {
-        const int it = a.st->it;
+        const int it = st->it;
         pold = (it & 1) ? a.p1 : a.p0;
         pnew = (it & 1) ? a.p0 : a.p1;
-        beta = a.st->beta;
+        beta = st->beta;
     }
     if (MODE == SPMV_SIGMA) src = pnew;
     if (MODE == SPMV_RESID) src = a.x;
@@ -109,7 +105,6 @@ __global__ __launch_bounds__(kWG) void k_spmv(SpmvArgs a) {
     const int32_t *__restrict__ rp = a.rp;
     const int32_t *__restrict__ ci = a.ci;
     const double *__restrict__ val = a.val;
-    double d0 = 0.0, d1 = 0.0;
     for (int base = r0; base < r1; base += RWG * U) {
         int kb[U], ke[U], row[U];
         double own[U];
@@ -183,6 +178,20 @@ __global__ __launch_bounds__(kWG) void k_spmv(SpmvArgs a) {
         }
     }
 
+}
+
+template <int GS, int MODE>
+__global__ __launch_bounds__(kWG) void k_spmv(SpmvArgs a) {
+    if (MODE == SPMV_LANCZOS) {
+        if (a.ls->done) return;
+    } else if (!(MODE == SPMV_RESID && a.resid_phase == 1)) {
+        if (a.st->done) return;
+    }
+    const int c = xcd_chunk(blockIdx.x, gridDim.x);
+    const int r0 = c * a.chunk;
+    const int r1 = min(r0 + a.chunk, a.n);
+    double d0 = 0.0, d1 = 0.0;
+    spmv_rows<GS, MODE>(a, a.st, r0, r1, d0, d1);
     const double v[2] = {d0, d1};
     block_partial<2>(v, a.partials);
 }

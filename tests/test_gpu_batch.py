@@ -1,4 +1,5 @@
-"""Batched persistent solver against per-system oracle solves."""
+"""Batched solver (every system advancing in the same launches) against
+per-system oracle solves."""
 import numpy as np
 import pytest
 import torch
@@ -8,24 +9,17 @@ from paper_2410_02408_amd import workloads as w
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
 
-# The persistent batched solve is switched off (bjp_batch_pcg_solve returns
-# EINVAL): its first GPU run did not return and no cause has been shown.
-PERSISTENT_OFF = pytest.mark.skip(reason="persistent batched solve switched off: first GPU run did not "
-                                         "return, cause not yet shown (see the design notes)")
-
-
 def small_batch(count=12, seed=5):
     mats, nbs, rhs = w.random_spd_batch(count, seed=seed, n_lo=100, n_hi=3000)
     return mats, nbs, rhs
 
 
-@PERSISTENT_OFF
-@pytest.mark.parametrize("lanes,threads", [(0, 0), (4, 256), (16, 1024), (32, 512)])
-def test_batch_matches_oracle(gpu, orc, lanes, threads):
+@pytest.mark.parametrize("lanes,tile_rows", [(0, 0), (4, 256), (16, 1024), (32, 4096)])
+def test_batch_matches_oracle(gpu, orc, lanes, tile_rows):
     mats, nbs, rhs = small_batch()
     B = gpu.Batch.from_systems(mats, nbs, DEV)
     M = gpu.batch_precondition(B)
-    x, info = gpu.batch_pcg_solve(B, M, np.concatenate(rhs), lanes=lanes, threads=threads)
+    x, info = gpu.batch_pcg_solve(B, M, np.concatenate(rhs), lanes=lanes, tile_rows=tile_rows)
     assert info.status == "OK" and info.systems_ok == len(mats)
     xs = x.cpu().numpy()
     for s, (A, nb, b) in enumerate(zip(mats, nbs, rhs)):
@@ -39,7 +33,6 @@ def test_batch_matches_oracle(gpu, orc, lanes, threads):
         assert abs(info.per_system["rel_res_true"][s] - res) <= 1e-13
 
 
-@PERSISTENT_OFF
 def test_batch_fp32_store(gpu, orc):
     mats, nbs, rhs = small_batch(6, seed=6)
     B = gpu.Batch.from_systems(mats, nbs, DEV)
@@ -78,7 +71,6 @@ def test_batch_not_spd_global_block_index(gpu):
     assert e.value.failed_block == (mats[0].n + 15) // 16 + 2
 
 
-@PERSISTENT_OFF
 def test_batch_autotune_picks_a_candidate(gpu, tmp_path, monkeypatch):
     from paper_2410_02408_amd import autotune
 
@@ -87,8 +79,8 @@ def test_batch_autotune_picks_a_candidate(gpu, tmp_path, monkeypatch):
     B = gpu.Batch.from_systems(mats, nbs, DEV)
     M = gpu.batch_precondition(B)
     cfg, timings = autotune.tune_batch(B, M, np.concatenate(rhs), probe_iters=5,
-                                       lanes=(4, 16), threads=(256, 512))
-    assert cfg["lanes"] in (4, 16) and cfg["threads"] in (256, 512) and len(timings) == 4
+                                       lanes=(4, 16), tile_rows=(256, 2048))
+    assert cfg["lanes"] in (4, 16) and cfg["tile_rows"] in (256, 2048) and len(timings) == 4
     cfg2, t2 = autotune.tune_batch(B, M, np.concatenate(rhs))
     assert cfg2 == cfg and t2 is None
     x, info = gpu.batch_pcg_solve(B, M, np.concatenate(rhs), **cfg)
