@@ -24,7 +24,7 @@ namespace bjp {
 enum SpmvMode { SPMV_DIR = 0, SPMV_SIGMA = 1, SPMV_RESID = 2, SPMV_LANCZOS = 3 };
 
 #ifndef BJP_SPMV_ROWS
-#define BJP_SPMV_ROWS 4
+#define BJP_SPMV_ROWS 2
 #endif
 // Rows each lane group keeps in flight per step.
 __host__ __device__ constexpr int spmv_rows_per_group(int gs) { return gs <= 16 ? BJP_SPMV_ROWS : 2; }
@@ -57,6 +57,20 @@ struct SpmvArgs {
     int has_m;
     double *partials;       // per-workgroup dots (see the modes)
 };
+
+#ifndef BJP_NT_CSR
+#define BJP_NT_CSR 0
+#endif
+// CSR values and column indices are streamed once per product; loading them
+// non-temporally keeps the gathered vector resident in the caches.
+template <typename T>
+__device__ __forceinline__ T csr_load(const T *p) {
+#if BJP_NT_CSR
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
 
 // The one place the updated direction is formed, so that the value gathered
 // by a neighbouring row and the value stored for the own row are identical.
@@ -130,8 +144,8 @@ __device__ __forceinline__ void spmv_rows(const SpmvArgs &a, const PcgState *st,
             for (int pp = 0; pp < NP; ++pp) {
                 const int k = kb[u] + sub + pp * GS;
                 const int kc = k < ke[u] ? k : 0;
-                col[u][pp] = ci[kc];
-                vv[u][pp] = val[kc];
+                col[u][pp] = csr_load(ci + kc);
+                vv[u][pp] = csr_load(val + kc);
             }
         }
 #pragma unroll
@@ -146,7 +160,7 @@ __device__ __forceinline__ void spmv_rows(const SpmvArgs &a, const PcgState *st,
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            for (int k = kb[u] + sub + NP * GS; k < ke[u]; k += GS) acc[u] += val[k] * gather(ci[k]);
+            for (int k = kb[u] + sub + NP * GS; k < ke[u]; k += GS) acc[u] += csr_load(val + k) * gather(csr_load(ci + k));
 #pragma unroll
         for (int u = 0; u < U; ++u) {
 #pragma unroll
