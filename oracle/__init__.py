@@ -139,6 +139,14 @@ def cholesky(tile) -> np.ndarray:
     return a
 
 
+def chol_solve(L, r) -> np.ndarray:
+    """Solve (L L^T) z = r with the oracle's forward/backward substitution."""
+    L = np.ascontiguousarray(L, dtype=np.float64)
+    z = np.empty(L.shape[0])
+    lib().orc_chol_solve(L.shape[0], L.ravel(), _vec(r), z)
+    return z
+
+
 class Precond:
     """Block-Jacobi preconditioner held as per-block Cholesky factors."""
 
