@@ -266,8 +266,25 @@ RowLaunch spmv_shape(int n, int gs) {
     return {grid, ceil_div(n, grid)};
 }
 
+// Compute units of the current device (cached per device).
+int device_cus() {
+    static int cus[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cus[dev] == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+        cus[dev] = v;
+    }
+    return cus[dev];
+}
+
+// The block-inverse application runs one workgroup per compute unit: each
+// wave streams a long run of packets through its two-stage pipeline, which
+// keeps more bytes in flight than more, shorter-lived waves (measured at
+// 128^3, n_b = 64: 117 us at 256 workgroups, 120 at 512, 127 at 768).
 RowLaunch apply_shape(int packets) {
-    const int grid = round8(std::min(ceil_div(packets, kWaves), kMaxRedWG));
+    const int grid = round8(std::min(ceil_div(packets, kWaves), std::min(device_cus(), kMaxRedWG)));
     return {grid, ceil_div(packets, grid)};
 }
 

@@ -131,20 +131,13 @@ __global__ __launch_bounds__(64) void k_setup(SetupArgs a) {
 // ---------------------------------------------------------------------------
 // Application
 // ---------------------------------------------------------------------------
-#ifndef BJP_APPLY_CHUNK
-#define BJP_APPLY_CHUNK 32
-#endif
-
-// z_i of one lane for one packet: D = the packet, rs = this lane's r (0 when
-// inactive), n = the lane's block size, i = lane index in its group.  The
-// diagonals are streamed KC at a time (a scheduling barrier between chunks
-// keeps at most KC of them live), so register use stays bounded for G = 64.
 #ifndef BJP_NT_TILES
 #define BJP_NT_TILES 1
 #endif
 // Tile loads: the packets are streamed once per application and exceed every
-// cache level, so they are loaded non-temporally (measured at 128^3, n_b = 64:
-// 130 us instead of 145 us per application, the vectors' lines stay cached).
+// cache level, so they are loaded non-temporally (the vectors' lines stay
+// cached; measured at 128^3, n_b = 64 with the unpipelined loop: 130 us
+// instead of 145 us per application).
 template <typename TS>
 __device__ __forceinline__ TS tile_load(const TS *p) {
 #if BJP_NT_TILES
@@ -154,39 +147,83 @@ __device__ __forceinline__ TS tile_load(const TS *p) {
 #endif
 }
 
-template <int G, typename TS, int KC = BJP_APPLY_CHUNK>
-__device__ __forceinline__ TS packet_apply(const TS *__restrict__ D, int lane, int g, int i, int n, TS rs) {
+// One packet, one wave: lane i of group g holds row i of block g.
+// packet_load issues the K + 1 loads of this lane's diagonal entries (the
+// half row counts as diagonal K = G/2); packet_product forms z_i from them.
+template <int G, typename TS>
+__device__ __forceinline__ void packet_load(const TS *__restrict__ D, int lane, int g, int i, TS (&dv)[G / 2 + 1]) {
     constexpr int K = G / 2;
+    dv[0] = tile_load(D + lane);
+#pragma unroll
+    for (int k = 1; k <= K; ++k) dv[k] = tile_load(k < K ? D + k * 64 + lane : D + K * 64 + g * K + (i & (K - 1)));
+}
+
+// Whole-wave rotations by one lane (DPP): kDppWaveRor1 gives lane i the
+// value of lane i-1, kDppWaveRol1 that of lane i+1 (lane indices mod 64).
+constexpr int kDppWaveRol1 = 0x134, kDppWaveRor1 = 0x13C;
+
+// (every lane is written, so no previous value of the destination is kept)
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// z = S r for one full 64 x 64 block held as cyclic diagonals dv[0..32]
+// (dv[32] is the half diagonal: lanes i and i + 32 hold the same entry).
+//   direct part      sum_k d_k[i] r[i+k]        k = 0 .. 32
+//   transposed part  sum_k d_k[i-k] r[i-k]      k = 1 .. 31
+// r[i+k] comes from k successive one-lane rotations of r; the transposed part
+// is evaluated Horner-style, acc_k = d_k r + (acc_{k+1} moved up one lane),
+// so only one-lane rotations are needed and no lane index is computed.
+template <typename TS>
+__device__ __forceinline__ TS full64_product(const TS (&dv)[33], TS rs) {
+    TS zd = dv[0] * rs;
+    TS rr = rs;
+#pragma unroll
+    for (int k = 1; k <= 32; ++k) {
+        rr = dpp_move<kDppWaveRol1>(rr);
+        zd += dv[k] * rr;
+    }
+    TS acc = dv[31] * rs;
+#pragma unroll
+    for (int k = 30; k >= 1; --k) acc = dv[k] * rs + dpp_move<kDppWaveRor1>(acc);
+    return zd + dpp_move<kDppWaveRor1>(acc);
+}
+
+// Any block size n <= G: entries are addressed modulo n, lanes i >= n and
+// the wrapped half of the middle diagonal are masked.  Full 64-row blocks
+// take the rotation form above.
+template <int G, typename TS>
+__device__ __forceinline__ TS packet_product(const TS (&dv)[G / 2 + 1], int g, int i, int n, TS rs) {
+    constexpr int K = G / 2;
+    if constexpr (G == 64) {
+        if (__builtin_amdgcn_readfirstlane(n) == 64) return full64_product<TS>(dv, rs);
+    }
     const bool act = i < n;
     const int ia = act ? i : 0;
     const int nn = n > 0 ? n : 1;
-    TS zv = tile_load(D + lane) * rs;
+    TS zv = dv[0] * rs;
 #pragma unroll
-    for (int k0 = 1; k0 <= K; k0 += KC) {
-        TS dv[KC];
-#pragma unroll
-        for (int kk = 0; kk < KC; ++kk) {
-            const int k = k0 + kk;
-            if (k <= K) dv[kk] = tile_load(k < K ? D + k * 64 + lane : D + K * 64 + g * K + (i & (K - 1)));
-        }
-#pragma unroll
-        for (int kk = 0; kk < KC; ++kk) {
-            const int k = k0 + kk;
-            if (k > K) break;
-            int j1 = ia + k;
-            if (j1 >= nn) j1 -= nn;
-            int j2 = ia - k;
-            if (j2 < 0) j2 += nn;
-            const TS rk = __shfl(rs, g * G + (j1 & (G - 1)), 64);
-            if (act && 2 * k <= n) zv += dv[kk] * rk;
-            const TS tv = (act && 2 * k < n) ? dv[kk] * rs : (TS)0;
-            const TS tt = __shfl(tv, g * G + (j2 & (G - 1)), 64);
-            if (act && 2 * k < n) zv += tt;
-        }
-        if (k0 + KC <= K) __builtin_amdgcn_sched_barrier(0);
+    for (int k = 1; k <= K; ++k) {
+        int j1 = ia + k;
+        if (j1 >= nn) j1 -= nn;
+        int j2 = ia - k;
+        if (j2 < 0) j2 += nn;
+        const TS rk = __shfl(rs, g * G + (j1 & (G - 1)), 64);
+        if (act && 2 * k <= n) zv += dv[k] * rk;
+        const TS tv = (act && 2 * k < n) ? dv[k] * rs : (TS)0;
+        const TS tt = __shfl(tv, g * G + (j2 & (G - 1)), 64);
+        if (act && 2 * k < n) zv += tt;
     }
     return zv;
 }
+
 enum ApplyMode { APPLY_PLAIN = 0, APPLY_INIT = 1, APPLY_UPDATE = 2, APPLY_LANCZOS = 3 };
 
 struct ApplyArgs {
@@ -229,40 +266,74 @@ __device__ __forceinline__ void apply_packets(const ApplyArgs &a, const PcgState
     const double *__restrict__ rin = a.rin;
     double *__restrict__ zout = a.zout;
     const int rend = a.row0 + a.n;
-    for (int pk = pk0; pk < pk1; pk += stride) {
+    // Two stages in turn: while the packet of one stage is multiplied, the
+    // loads of the next packet fill the other.  Unrolled by two so that no
+    // register copy (which would wait for the pending loads) is needed.
+    constexpr int NV = MODE == APPLY_UPDATE ? 4 : 1;
+    constexpr int ND = G / 2 + 1;
+    struct Stage {
+        TS d[ND];
+        double v[NV];
+        int s, n;
+    };
+    auto stage_load = [&](Stage &S, int pk) {
         const int t = pk * P + g;
-        int s = 0, n = 0;
         if (a.uniform_nb > 0) {
-            s = a.row0 + t * a.uniform_nb;
-            n = max(0, min(a.uniform_nb, rend - s));
+            S.s = a.row0 + t * a.uniform_nb;
+            S.n = max(0, min(a.uniform_nb, rend - S.s));
         } else {
             const int tc = min(t, a.nblocks - 1);
             const int s0 = off[tc], e0 = off[tc + 1];
-            s = t < a.nblocks ? s0 : 0;
-            n = t < a.nblocks ? e0 - s0 : 0;
+            S.s = t < a.nblocks ? s0 : 0;
+            S.n = t < a.nblocks ? e0 - s0 : 0;
         }
-        const bool act = i < n;
-        const int row = s + i;
-        const int rc = min(row, rend - 1);      // in-bounds index for masked lanes
+        const int rc = min(S.s + i, rend - 1);    // in-bounds index for masked lanes
+        if (MODE == APPLY_UPDATE) {
+            S.v[0] = xv_[rc];
+            S.v[1] = pn[rc];
+            S.v[2] = qv_[rc];
+            S.v[3] = rv_[rc];
+        } else {
+            S.v[0] = rin[rc];
+        }
+        packet_load<G, TS>(tiles + (size_t)pk * E, lane, g, i, S.d);
+    };
+    auto stage_apply = [&](const Stage &S) {
+        const bool act = i < S.n;
+        const int row = S.s + i;
         double rv;
         if (MODE == APPLY_UPDATE) {
-            const double xo = xv_[rc], pv = pn[rc], qv = qv_[rc], ro = rv_[rc];
-            rv = act ? fma(-alpha, qv, ro) : 0.0;
-            if (act) {
-                xv_[row] = fma(alpha, pv, xo);
+            rv = act ? fma(-alpha, S.v[2], S.v[3]) : 0.0;
+        } else {
+            rv = act ? S.v[0] : 0.0;
+        }
+        const TS zv = packet_product<G, TS>(S.d, g, i, S.n, (TS)rv);
+        if (act) {
+            if (MODE == APPLY_UPDATE) {
+                xv_[row] = fma(alpha, S.v[1], S.v[0]);
                 rv_[row] = rv;
             }
-        } else {
-            const double ro = rin[rc];
-            rv = act ? ro : 0.0;
-        }
-        const TS zv = packet_apply<G, TS>(tiles + (size_t)pk * E, lane, g, i, n, (TS)rv);
-        if (act) {
             const double z = (double)zv;
             zout[row] = z;
             d0 += rv * z;
             d1 += rv * rv;
         }
+    };
+    if (pk0 >= pk1) return;
+    Stage A, B;
+    stage_load(A, pk0);
+    for (int pk = pk0;;) {
+        // past the end the current packet is loaded again: loads stay in bounds
+        stage_load(B, pk + stride < pk1 ? pk + stride : pk);
+        __builtin_amdgcn_sched_barrier(0);
+        stage_apply(A);
+        pk += stride;
+        if (pk >= pk1) break;
+        stage_load(A, pk + stride < pk1 ? pk + stride : pk);
+        __builtin_amdgcn_sched_barrier(0);
+        stage_apply(B);
+        pk += stride;
+        if (pk >= pk1) break;
     }
 }
 
