@@ -131,7 +131,7 @@ int bjp_apply(const bjp_precond_t *M, const double *r, double *z, hipStream_t st
  * created and destroyed by the caller (host array of 2*capacity handles). */
 typedef enum {
     BJP_KERNEL_APPLY = 0,   /* the block-inverse application (x, r update + z = M^-1 r) */
-    BJP_KERNEL_SPMV = 1     /* the sparse product q = A p (with the fused direction) */
+    BJP_KERNEL_SPMV = 1     /* the sparse product q = A p                           */
 } bjp_kernel_id;
 
 typedef struct {
@@ -149,8 +149,9 @@ typedef struct {
     int32_t x0_given;         /* 1: x holds the starting guess; 0: start from 0     */
     int32_t max_replacements; /* true-residual restarts (default 3; <0 means none)  */
     int32_t check_every;      /* iterations between convergence polls (default 16) */
-    int32_t spmv_lanes;       /* lanes per CSR row: 0 = auto, else 1,2,..,64       */
-    int32_t fuse_direction;   /* -1 = auto, 0 = separate p update, 1 = fused in SpMV */
+    int32_t spmv_lanes;       /* CSR product schedule: 0 = auto, 1,2,..,64 = lanes
+                                 per row, < 0 = row blocks streamed through LDS    */
+    int32_t pad;
     double *history;          /* device, optional, >= max_iter+1 entries: recursive
                                  relative residual after each iteration             */
     bjp_timing_t *timing;     /* host, optional kernel timing (see bjp_timing_t)    */

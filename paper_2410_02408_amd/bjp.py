@@ -49,7 +49,7 @@ class TimingT(C.Structure):
 class PcgOptsT(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("x0_given", C.c_int32),
                 ("max_replacements", C.c_int32), ("check_every", C.c_int32),
-                ("spmv_lanes", C.c_int32), ("fuse_direction", C.c_int32),
+                ("spmv_lanes", C.c_int32), ("pad", C.c_int32),
                 ("history", C.c_void_p), ("timing", C.c_void_p)]
 
 
@@ -268,7 +268,7 @@ class PcgWorkspace:
 
 def pcg_solve(A: DeviceCsr, M: Precond | None, b, tol: float = 1e-10, max_iter: int | None = None,
               x0=None, out: torch.Tensor | None = None, max_replacements: int = 3,
-              check_every: int = 0, spmv_lanes: int = 0, fuse_direction: int = -1,
+              check_every: int = 0, spmv_lanes: int = 0,
               history: torch.Tensor | None = None, workspace: PcgWorkspace | None = None,
               timer: KernelTimer | None = None):
     """bjp_pcg_solve.  Returns (x, PcgInfo); solver failures are reported in
@@ -285,7 +285,7 @@ def pcg_solve(A: DeviceCsr, M: Precond | None, b, tol: float = 1e-10, max_iter: 
     ws = workspace or PcgWorkspace(A)
     opts = PcgOptsT(tol, int(max_iter or 0), 1 if x0 is not None else 0,
                     -1 if max_replacements == 0 else int(max_replacements), int(check_every),
-                    int(spmv_lanes), int(fuse_direction),
+                    int(spmv_lanes), 0,
                     history.data_ptr() if history is not None else None,
                     C.cast(C.pointer(timer.struct), C.c_void_p) if timer is not None else None)
     info = PcgInfoT()

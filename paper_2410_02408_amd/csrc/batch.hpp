@@ -76,7 +76,11 @@ __global__ __launch_bounds__(kWG) void k_apply_tiles(ApplyArgs a, TileSpan ts) {
             b.uniform_nb = si.nb;
             b.nblocks = si.nblocks;
             b.tiles = static_cast<const TS *>(a.tiles) + si.tile0;
-            apply_packets<G, TS, MODE>(b, st, tl.a0 + (threadIdx.x >> 6), tl.a1, kWaves, d0, d1);
+            auto pre = [&](double &alpha) -> bool {
+                if (MODE == APPLY_UPDATE) alpha = st->alpha;
+                return true;
+            };
+            apply_packets<G, TS, MODE>(b, st, tl.a0 + (threadIdx.x >> 6), tl.a1, kWaves, d0, d1, pre);
         }
     }
     const double v[2] = {d0, d1};

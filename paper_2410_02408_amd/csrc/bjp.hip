@@ -106,7 +106,7 @@ __global__ void k_pcg_state_init(PcgState *st, double tol, int max_iter) {
     st->status = BJP_OK;
     st->max_iter = max_iter;
     st->zero_rhs = 0;
-    st->pad = 0;
+    st->pending = 0;
 }
 
 __global__ void k_pcg_restart(PcgState *st) {
@@ -241,9 +241,11 @@ void launch_apply(const bjp_precond_t *M, int grid, const ApplyArgs &a, hipStrea
     else launch_apply_t<double, MODE>(M->group, grid, a, s);
 }
 
+// gs = lanes per row of the lane-group schedule, 0 = row-block streaming.
 template <int MODE>
 void launch_spmv(int gs, int grid, const SpmvArgs &a, hipStream_t s) {
     switch (gs) {
+        case 0: hipLaunchKernelGGL((k_spmv_stream<MODE>), dim3(grid), dim3(kWG), 0, s, a); break;
         case 1: hipLaunchKernelGGL((k_spmv<1, MODE>), dim3(grid), dim3(kWG), 0, s, a); break;
         case 2: hipLaunchKernelGGL((k_spmv<2, MODE>), dim3(grid), dim3(kWG), 0, s, a); break;
         case 4: hipLaunchKernelGGL((k_spmv<4, MODE>), dim3(grid), dim3(kWG), 0, s, a); break;
@@ -260,6 +262,13 @@ struct RowLaunch {
 };
 
 RowLaunch spmv_shape(int n, int gs) {
+    if (gs == 0) {
+        // whole row blocks per workgroup
+        const int blocks = ceil_div(std::max(n, 1), kStreamRows);
+        const int per = ceil_div(blocks, kMaxRedWG);
+        const int chunk = per * kStreamRows;
+        return {round8(ceil_div(std::max(n, 1), chunk)), chunk};
+    }
     const int u = spmv_rows_per_group(gs);
     const int rows_per_step = (kWG / gs) * u;
     const int grid = round8(std::min(ceil_div(n, rows_per_step), kMaxRedWG));
@@ -320,6 +329,23 @@ int auto_lanes(const bjp_csr_t *A) {
     int gs = 1;
     while (gs < 64 && 2 * gs <= mean) gs <<= 1;
     return gs;
+}
+
+#ifndef BJP_STREAM_MEAN
+#define BJP_STREAM_MEAN 12.0
+#endif
+// Schedule of the single-system products: row-block streaming (0) for short
+// rows, else the lane-group schedule with auto_lanes lanes.
+int auto_spmv(const bjp_csr_t *A) {
+    if (A->n > 0 && (double)A->nnz / A->n < BJP_STREAM_MEAN) return 0;
+    return auto_lanes(A);
+}
+
+// Schedule from the user's option: > 0 lanes per row, < 0 streaming, 0 auto.
+int spmv_schedule(int opt, const bjp_csr_t *A) {
+    if (opt > 0) return pow2_at_least(std::min(opt, 64));
+    if (opt < 0) return 0;
+    return auto_spmv(A);
 }
 
 // ---------------------------------------------------------------------------
@@ -556,7 +582,7 @@ int bjp_pcg_workspace(const bjp_csr_t *A, size_t *bytes) {
     *bytes = 0;
     if (check_csr_host(A) != BJP_OK) return BJP_EINVAL;
     const size_t vec = al256(sizeof(double) * (size_t)std::max(A->n, 1));
-    *bytes = 5 * vec + al256(sizeof(double) * 2 * kMaxRedWG) + al256(sizeof(PcgState)) + 2 * al256(64);
+    *bytes = 5 * vec + 2 * al256(sizeof(double) * 2 * kMaxRedWG) + 2 * al256(sizeof(PcgState)) + 2 * al256(64);
     return BJP_OK;
 }
 
@@ -588,8 +614,16 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
     Carver cv{static_cast<char *>(ws)};
     double *r = cv.take<double>(n), *z = cv.take<double>(n), *p0 = cv.take<double>(n);
     double *p1 = cv.take<double>(n), *q = cv.take<double>(n);
+    // partials of the products (p^T A p, residual norms) and of the
+    // preconditioner applications (r^T z, r^T r) are kept apart: each
+    // streaming launch reads the other's as the input of its decision
     double *partials = cv.take<double>(2 * kMaxRedWG);
+    double *partials_a = cv.take<double>(2 * kMaxRedWG);
+    // st: the state between iterations (after the application); st1: after
+    // the direction update.  Each iteration's two deciding launches read one
+    // and record the other.
     PcgState *st = cv.take<PcgState>(1);
+    PcgState *st1 = cv.take<PcgState>(1);
     int32_t *flags = cv.take<int32_t>(16);
     double *zeros = cv.take<double>(8);
     if (!M) z = r;  // plain CG: the "preconditioned" residual is r itself
@@ -597,10 +631,7 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
     int s = run_validate(A, flags, stream);
     if (s != BJP_OK) return fail(s);
 
-    const int gs = o.spmv_lanes > 0 ? pow2_at_least(std::min(o.spmv_lanes, 64)) : auto_lanes(A);
-    // Separate direction update by default: forming p on the fly in the SpMV
-    // doubles its gathers and measured slower on every workload tried.
-    const bool fuse = o.fuse_direction > 0;
+    const int gs = spmv_schedule(o.spmv_lanes, A);
     const RowLaunch Ls = spmv_shape(n, gs);
     const RowLaunch La = M ? apply_shape(M->num_packets) : rows_shape(n);
     const int fill_grid = std::min(ceil_div(n, kWG), 4096);
@@ -618,7 +649,6 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
     sa.ci = A->nnz > 0 ? A->col_idx : reinterpret_cast<const int32_t *>(zeros);
     sa.val = A->nnz > 0 ? A->val : zeros;
     sa.st = st;
-    sa.z = z;
     sa.p0 = p0;
     sa.p1 = p1;
     sa.q = q;
@@ -650,13 +680,23 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
     aa.q = q;
     aa.p0 = p0;
     aa.p1 = p1;
-    aa.partials = partials;
+    aa.partials = partials_a;
+    // the iteration's application reads st1 and the product's partials
+    ApplyArgs au = aa;
+    au.st = st1;
+    au.st_out = st;
+    au.dec_partials = partials;
+    au.dec_nparts = Ls.grid;
+    SpmvArgs su = sa;
+    su.st = st1;
+    FinishArgs fu = fa;
+    fu.partials = partials_a;
 
     auto start_direction = [&]() {
         if (M) launch_apply<APPLY_INIT>(M, La.grid, aa, stream);
         else hipLaunchKernelGGL((k_rows_update<APPLY_INIT>), dim3(La.grid), dim3(kWG), 0, stream, aa, n,
                                 La.chunk);
-        finish<FIN_PCG_START>(fa, La.grid, stream);
+        finish<FIN_PCG_START>(fu, La.grid, stream);
     };
     bjp_timing_t *tm = o.timing;
     if (tm) tm->recorded = 0;
@@ -665,27 +705,38 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
         (void)hipEventRecord(tm->events[2 * tm->recorded + which], stream);
         if (which == 1) tm->recorded++;
     };
+    // One iteration is three launches, each taking the scalar decision of the
+    // previous one as its prologue (no separate finish launches):
+    //   direction     update decision (rho, beta, convergence) -> st1; p = z + beta p
+    //   product       q = A p, partials of p^T q
+    //   application   alpha = rho / p^T q -> st; x += alpha p, r -= alpha q,
+    //                 z = M^-1 r, partials of r^T z, r^T r (decision pending)
+    const int dir_grid = std::min(ceil_div(n, kWG * kDirRows), 2048);
     auto iteration = [&]() {
-        if (fuse) {
-            mark(BJP_KERNEL_SPMV, 0);
-            launch_spmv<SPMV_DIR>(gs, Ls.grid, sa, stream);
-            mark(BJP_KERNEL_SPMV, 1);
-        } else {
-            hipLaunchKernelGGL(k_direction, dim3(fill_grid), dim3(kWG), 0, stream, st, z, p0, p1, n);
-            mark(BJP_KERNEL_SPMV, 0);
-            launch_spmv<SPMV_SIGMA>(gs, Ls.grid, sa, stream);
-            mark(BJP_KERNEL_SPMV, 1);
-        }
-        finish<FIN_SIGMA>(fa, Ls.grid, stream);
+        if (M)
+            hipLaunchKernelGGL((k_direction<FIN_PCG_UPDATE>), dim3(dir_grid), dim3(kWG), 0, stream, st, st1,
+                               partials_a, La.grid, o.history, z, p0, p1, n);
+        else
+            hipLaunchKernelGGL((k_direction<FIN_PCG_UPDATE_I>), dim3(dir_grid), dim3(kWG), 0, stream, st, st1,
+                               partials_a, La.grid, o.history, z, p0, p1, n);
+        mark(BJP_KERNEL_SPMV, 0);
+        launch_spmv<SPMV_SIGMA>(gs, Ls.grid, su, stream);
+        mark(BJP_KERNEL_SPMV, 1);
         mark(BJP_KERNEL_APPLY, 0);
-        if (M) launch_apply<APPLY_UPDATE>(M, La.grid, aa, stream);
-        else hipLaunchKernelGGL((k_rows_update<APPLY_UPDATE>), dim3(La.grid), dim3(kWG), 0, stream, aa,
+        if (M) launch_apply<APPLY_UPDATE>(M, La.grid, au, stream);
+        else hipLaunchKernelGGL((k_rows_update<APPLY_UPDATE>), dim3(La.grid), dim3(kWG), 0, stream, au,
                                 n, La.chunk);
         mark(BJP_KERNEL_APPLY, 1);
-        if (M) finish<FIN_PCG_UPDATE>(fa, La.grid, stream);
-        else finish<FIN_PCG_UPDATE_I>(fa, La.grid, stream);
+    };
+    // before the host reads st: take a pending update decision in place
+    auto commit = [&]() {
+        FinishArgs g = fu;
+        g.nparts = La.grid;
+        if (M) hipLaunchKernelGGL((k_finish_commit<FIN_PCG_UPDATE>), dim3(1), dim3(kWG), 0, stream, g);
+        else hipLaunchKernelGGL((k_finish_commit<FIN_PCG_UPDATE_I>), dim3(1), dim3(kWG), 0, stream, g);
     };
     auto read_state = [&](PcgState &h) -> int {
+        commit();
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipMemcpyAsync(&h, st, sizeof(PcgState), hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
@@ -814,7 +865,7 @@ int bjp_kappa_estimate(const bjp_csr_t *A, const bjp_precond_t *M, const double 
     int s = run_validate(A, flags, stream);
     if (s != BJP_OK) return fail(s);
 
-    const int gs = auto_lanes(A);
+    const int gs = auto_spmv(A);
     const RowLaunch Ls = spmv_shape(n, gs);
     const RowLaunch Lr = rows_shape(n);
     hipLaunchKernelGGL(k_lanczos_state_init, dim3(1), dim3(64), 0, stream, ls, steps);
@@ -1075,7 +1126,6 @@ int bjp_batch_pcg_solve(const bjp_csr_t *A, const bjp_batch_t *B, const bjp_batc
     sa.ci = A->col_idx;
     sa.val = A->val;
     sa.st = states;
-    sa.z = z;
     sa.p0 = p0;
     sa.p1 = p1;
     sa.q = q;

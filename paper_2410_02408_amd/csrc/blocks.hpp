@@ -23,6 +23,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "finish.hpp"
 
 namespace bjp {
 
@@ -235,7 +236,10 @@ struct ApplyArgs {
     const void *tiles;
     const double *rin;      // PLAIN / INIT / LANCZOS: residual to precondition
     double *zout;           // PLAIN / INIT / LANCZOS / UPDATE: z = M^-1 r
-    PcgState *st;           // INIT / UPDATE
+    PcgState *st;           // INIT / UPDATE (UPDATE: the state after the direction update)
+    PcgState *st_out;       // UPDATE: where workgroup 0 records the state with alpha
+    const double *dec_partials;  // UPDATE: partials of p^T A p from the product
+    int dec_nparts;
     double *x, *r;          // UPDATE: x += alpha p, r -= alpha q
     const double *q;
     double *p0, *p1;        // UPDATE: p_new = p[(it+1)&1]
@@ -245,19 +249,19 @@ struct ApplyArgs {
 
 // Packets pk0, pk0 + stride, ... < pk1 of one system (rows [a.row0,
 // a.row0 + a.n), tiles at a.tiles) in the given mode; accumulates this
-// thread's share of r^T z and r^T r.  One wave per packet.
-template <int G, typename TS, int MODE>
+// thread's share of r^T z and r^T r.  One wave per packet.  `st` gives the
+// iteration count (the direction buffer); pre(alpha), called by every thread
+// once the first packet's loads are issued, supplies the step length and
+// returns false to skip the work.
+template <int G, typename TS, int MODE, typename Pre>
 __device__ __forceinline__ void apply_packets(const ApplyArgs &a, const PcgState *st, int pk0, int pk1, int stride,
-                                              double &d0, double &d1) {
+                                              double &d0, double &d1, Pre pre) {
     constexpr int P = 64 / G, E = packet_elems(G);
     const int lane = threadIdx.x & 63;
     const int g = lane / G, i = lane % G;
     double alpha = 0.0;
     const double *__restrict__ pn = nullptr;
-    if (MODE == APPLY_UPDATE) {
-        alpha = st->alpha;
-        pn = ((st->it + 1) & 1) ? a.p1 : a.p0;
-    }
+    if (MODE == APPLY_UPDATE) pn = ((st->it + 1) & 1) ? a.p1 : a.p0;
     const TS *__restrict__ tiles = static_cast<const TS *>(a.tiles);
     const int32_t *__restrict__ off = a.off;
     double *__restrict__ xv_ = a.x;
@@ -288,7 +292,7 @@ __device__ __forceinline__ void apply_packets(const ApplyArgs &a, const PcgState
             S.n = t < a.nblocks ? e0 - s0 : 0;
         }
         const int rc = min(S.s + i, rend - 1);    // in-bounds index for masked lanes
-        if (MODE == APPLY_UPDATE) {
+        if constexpr (MODE == APPLY_UPDATE) {
             S.v[0] = xv_[rc];
             S.v[1] = pn[rc];
             S.v[2] = qv_[rc];
@@ -302,14 +306,14 @@ __device__ __forceinline__ void apply_packets(const ApplyArgs &a, const PcgState
         const bool act = i < S.n;
         const int row = S.s + i;
         double rv;
-        if (MODE == APPLY_UPDATE) {
+        if constexpr (MODE == APPLY_UPDATE) {
             rv = act ? fma(-alpha, S.v[2], S.v[3]) : 0.0;
         } else {
             rv = act ? S.v[0] : 0.0;
         }
         const TS zv = packet_product<G, TS>(S.d, g, i, S.n, (TS)rv);
         if (act) {
-            if (MODE == APPLY_UPDATE) {
+            if constexpr (MODE == APPLY_UPDATE) {
                 xv_[row] = fma(alpha, S.v[1], S.v[0]);
                 rv_[row] = rv;
             }
@@ -319,9 +323,10 @@ __device__ __forceinline__ void apply_packets(const ApplyArgs &a, const PcgState
             d1 += rv * rv;
         }
     };
-    if (pk0 >= pk1) return;
+    const bool any = pk0 < pk1;
     Stage A, B;
-    stage_load(A, pk0);
+    if (any) stage_load(A, pk0);
+    if (!pre(alpha) || !any) return;
     for (int pk = pk0;;) {
         // past the end the current packet is loaded again: loads stay in bounds
         stage_load(B, pk + stride < pk1 ? pk + stride : pk);
@@ -337,9 +342,12 @@ __device__ __forceinline__ void apply_packets(const ApplyArgs &a, const PcgState
     }
 }
 
+// UPDATE first takes the step-length decision alpha = rho / (p^T A p) in
+// every workgroup (from the product's partials), then updates x and r,
+// applies M^-1 and marks the update decision pending for the next launch.
 template <int G, typename TS, int MODE>
 __global__ __launch_bounds__(kWG) void k_apply(ApplyArgs a) {
-    if (MODE == APPLY_INIT || MODE == APPLY_UPDATE) {
+    if (MODE == APPLY_INIT) {
         if (a.st->done) return;
     }
     if (MODE == APPLY_LANCZOS) {
@@ -350,7 +358,13 @@ __global__ __launch_bounds__(kWG) void k_apply(ApplyArgs a) {
     const int pk0 = c * a.chunk;
     const int pk1 = min(pk0 + a.chunk, a.num_packets);
     double d0 = 0.0, d1 = 0.0;
-    apply_packets<G, TS, MODE>(a, a.st, pk0 + wave, pk1, kWaves, d0, d1);
+    auto pre = [&](double &alpha) -> bool {
+        if (MODE != APPLY_UPDATE) return true;
+        const PcgState L = shared_decide<FIN_SIGMA>(a.st, a.st_out, a.dec_partials, a.dec_nparts, nullptr, true);
+        alpha = L.alpha;
+        return !L.done;
+    };
+    apply_packets<G, TS, MODE>(a, a.st, pk0 + wave, pk1, kWaves, d0, d1, pre);
     if (MODE == APPLY_PLAIN) return;
     const double v[2] = {d0, d1};
     block_partial<2>(v, a.partials);
@@ -359,14 +373,22 @@ __global__ __launch_bounds__(kWG) void k_apply(ApplyArgs a) {
 // Preconditioner-free (M = I) counterpart of k_apply for PCG: z is r itself.
 template <int MODE>
 __global__ __launch_bounds__(kWG) void k_rows_update(ApplyArgs a, int n, int chunk) {
-    if (a.st->done) return;
+    PcgState L;
+    const PcgState *st = a.st;
+    if (MODE == APPLY_UPDATE) {
+        L = shared_decide<FIN_SIGMA>(a.st, a.st_out, a.dec_partials, a.dec_nparts, nullptr, true);
+        if (L.done) return;
+        st = &L;
+    } else if (a.st->done) {
+        return;
+    }
     const int c = xcd_chunk(blockIdx.x, gridDim.x);
     const int r0 = c * chunk, r1 = min(r0 + chunk, n);
     double alpha = 0.0;
     const double *pn = nullptr;
     if (MODE == APPLY_UPDATE) {
-        alpha = a.st->alpha;
-        pn = ((a.st->it + 1) & 1) ? a.p1 : a.p0;
+        alpha = st->alpha;
+        pn = ((st->it + 1) & 1) ? a.p1 : a.p0;
     }
     double d1 = 0.0;
     for (int row = r0 + threadIdx.x; row < r1; row += kWG) {

@@ -104,18 +104,43 @@ __device__ __forceinline__ void sum_partials_range(const double *partials, int s
     }
 }
 
+// This thread's share of the partials: partials[q * nparts + b] for
+// b = tid, tid + 256, ..., summed in that order (nparts >= 1).  The loads of
+// the first kMaxRedWG partials are issued before the first is used (clamped
+// index, masked value; rounds past nparts are skipped for the whole
+// workgroup).
+template <int NQ>
+__device__ __forceinline__ void thread_partials(const double *partials, int nparts, double (&acc)[NQ]) {
+    constexpr int PER = kMaxRedWG / kWG;
+    const int tid = threadIdx.x;
+    double v[NQ][PER];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int j = 0; j < PER; ++j)
+            v[q][j] = j * kWG < nparts ? partials[q * nparts + min(tid + j * kWG, nparts - 1)] : 0.0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        acc[q] = 0.0;
+#pragma unroll
+        for (int j = 0; j < PER; ++j)
+            if (tid + j * kWG < nparts) acc[q] += v[q][j];
+        for (int b = tid + PER * kWG; b < nparts; b += kWG) acc[q] += partials[q * nparts + b];
+    }
+}
+
 // Sum of partials[q * nparts + b] over b, in a fixed order, for a
 // one-workgroup launch; every thread receives the totals.
 template <int NQ>
 __device__ __forceinline__ void sum_partials(const double *partials, int nparts, double (&out)[NQ]) {
     __shared__ double red[NQ][kWaves];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double acc[NQ];
+    thread_partials<NQ>(partials, nparts, acc);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        double acc = 0.0;
-        for (int b = tid; b < nparts; b += kWG) acc += partials[q * nparts + b];
-        acc = wave_sum(acc);
-        if (lane == 0) red[q][wave] = acc;
+        acc[q] = wave_sum(acc[q]);
+        if (lane == 0) red[q][wave] = acc[q];
     }
     __syncthreads();
 #pragma unroll
@@ -127,8 +152,8 @@ __device__ __forceinline__ void sum_partials(const double *partials, int nparts,
 }
 
 // ---------------------------------------------------------------------------
-// Device-resident solver state.  Written only by the last workgroup of a
-// launch (thread 0), read by every thread of the following launches.
+// Device-resident solver state.  Written by thread 0 of one workgroup of a
+// launch, read by every thread of the following launches.
 // ---------------------------------------------------------------------------
 struct PcgState {
     double rho;        // r^T z of the current iterate
@@ -143,7 +168,7 @@ struct PcgState {
     int32_t status;    // bjp_status
     int32_t max_iter;
     int32_t zero_rhs;  // b == 0
-    int32_t pad;
+    int32_t pending;   // 1: the partials hold r^T z, r^T r of an update not yet decided
 };
 
 struct LanczosState {

@@ -97,6 +97,8 @@ __device__ __forceinline__ bool finish_runs(const PcgState *st, const LanczosSta
     return !st->done;
 }
 
+constexpr bool is_update_op(int op) { return op == FIN_PCG_UPDATE || op == FIN_PCG_UPDATE_I; }
+
 // The scalar decision of OP from the totals (thread 0 only).
 template <int OP>
 __device__ __forceinline__ void finish_decide(const FinishArgs &f, PcgState *st, LanczosState *ls,
@@ -133,8 +135,10 @@ __device__ __forceinline__ void finish_decide(const FinishArgs &f, PcgState *st,
         pcg_after_init(st, out[0]);
     } else if (OP == FIN_PCG_UPDATE) {
         pcg_after_update(st, out[0], out[NQ - 1], f.hist);
+        st->pending = 0;
     } else if (OP == FIN_PCG_UPDATE_I) {
         pcg_after_update(st, out[0], out[0], f.hist);
+        st->pending = 0;
     } else if (OP == FIN_LZ_START) {
         const double bb = out[0];
         if (!(bb > 0.0)) {
@@ -166,6 +170,97 @@ __global__ __launch_bounds__(kWG) void k_finish(FinishArgs f) {
     double out[NQ];
     sum_partials<NQ>(f.partials, f.nparts, out);
     if (threadIdx.x == 0) finish_decide<OP>(f, f.st, f.ls, out);
+}
+
+// Update decisions are deferred: the launch that forms r^T z and r^T r marks
+// the state pending, and the decision is taken by whichever comes first, the
+// prologue of the next direction update or a commit before the host reads
+// the state.
+template <int OP>
+__global__ __launch_bounds__(kWG) void k_finish_commit(FinishArgs f) {
+    static_assert(is_update_op(OP), "update decisions only");
+    constexpr int NQ = finish_nq<OP>();
+    if (!finish_runs<OP>(f.st, f.ls) || !f.st->pending) return;
+    double out[NQ];
+    sum_partials<NQ>(f.partials, f.nparts, out);
+    if (threadIdx.x == 0) finish_decide<OP>(f, f.st, f.ls, out);
+}
+
+// The same decision taken redundantly by every thread of a streaming
+// launch, as its prologue: each workgroup sums the partials of the previous
+// launch in the fixed order of sum_partials, so every thread reaches the
+// identical state, which is returned; workgroup 0 records it at dst.  The
+// state is read with uniform (scalar) loads, independent of the vector loads
+// the launch may already have in flight.  dst must not be src: other
+// workgroups may still be reading src.  With mark_pending the recorded state
+// also marks the update the launch is about to form as pending (unless the
+// solve is done).  Must be called by every thread, once per launch.
+// Field-wise copies of the solver state (whole-struct copies leave a private
+// stack object behind, which the compiler then places in LDS per thread).
+__device__ __forceinline__ PcgState load_state(const PcgState *__restrict__ s) {
+    PcgState L;
+    L.rho = s->rho;
+    L.alpha = s->alpha;
+    L.beta = s->beta;
+    L.bnorm2 = s->bnorm2;
+    L.tol = s->tol;
+    L.relres = s->relres;
+    L.relres_true = s->relres_true;
+    L.it = s->it;
+    L.done = s->done;
+    L.status = s->status;
+    L.max_iter = s->max_iter;
+    L.zero_rhs = s->zero_rhs;
+    L.pending = s->pending;
+    return L;
+}
+__device__ __forceinline__ void store_state(PcgState *d, const PcgState &L) {
+    d->rho = L.rho;
+    d->alpha = L.alpha;
+    d->beta = L.beta;
+    d->bnorm2 = L.bnorm2;
+    d->tol = L.tol;
+    d->relres = L.relres;
+    d->relres_true = L.relres_true;
+    d->it = L.it;
+    d->done = L.done;
+    d->status = L.status;
+    d->max_iter = L.max_iter;
+    d->zero_rhs = L.zero_rhs;
+    d->pending = L.pending;
+}
+
+template <int OP>
+__device__ __forceinline__ PcgState shared_decide(const PcgState *__restrict__ src, PcgState *dst,
+                                                  const double *partials, int nparts, double *hist,
+                                                  bool mark_pending = false) {
+    constexpr int NQ = finish_nq<OP>();
+    __shared__ double red[NQ][kWaves];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    PcgState L = load_state(src);
+    double acc[NQ];
+    thread_partials<NQ>(partials, nparts, acc);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const double v = wave_sum(acc[q]);
+        if (lane == 0) red[q][wave] = v;
+    }
+    __syncthreads();
+    if (finish_runs<OP>(&L, nullptr) && (!is_update_op(OP) || L.pending)) {
+        double out[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            double t = 0.0;
+            for (int w = 0; w < kWaves; ++w) t += red[q][w];
+            out[q] = t;
+        }
+        FinishArgs f{};
+        f.hist = (blockIdx.x == 0 && tid == 0) ? hist : nullptr;
+        finish_decide<OP>(f, &L, nullptr, out);
+    }
+    if (mark_pending && !L.done) L.pending = 1;
+    if (blockIdx.x == 0 && tid == 0) store_state(dst, L);
+    return L;
 }
 
 // Batched form: workgroup s decides for system s from the partials of its

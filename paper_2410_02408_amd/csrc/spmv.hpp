@@ -9,19 +9,18 @@
 // row length (short stencil rows: GS = 8; long power-law rows: GS = 32..64).
 //
 // Modes (what is gathered, what is written, which dots are reduced):
-//   DIR     p_new = z + beta p_old is formed on the fly for every gathered
-//           column and for the own row (stored); q = A p_new; sigma = p^T q.
-//   SIGMA   q = A p for a p already updated; sigma = p^T q.
+//   SIGMA   q = A p for the current direction p; sigma = p^T q.
 //   RESID   r = b - A x; ||b||^2 and ||r||^2.
 //   LANCZOS v_j = z~ / beta, u_j = r~ / beta are normalised on the fly and
 //           stored; w = A v_j; alpha_j = v_j^T w.
 #pragma once
 
 #include "common.hpp"
+#include "finish.hpp"
 
 namespace bjp {
 
-enum SpmvMode { SPMV_DIR = 0, SPMV_SIGMA = 1, SPMV_RESID = 2, SPMV_LANCZOS = 3 };
+enum SpmvMode { SPMV_SIGMA = 0, SPMV_RESID = 1, SPMV_LANCZOS = 2 };
 
 #ifndef BJP_SPMV_ROWS
 #define BJP_SPMV_ROWS 2
@@ -42,9 +41,8 @@ struct SpmvArgs {
     const int32_t *rp, *ci;
     const double *val;
     PcgState *st;
-    const double *z;        // DIR: preconditioned residual
-    double *p0, *p1;        // DIR/SIGMA: direction ping-pong, selected by st->it
-    double *q;              // DIR/SIGMA: q = A p
+    double *p0, *p1;        // SIGMA: direction ping-pong, selected by st->it
+    double *q;              // SIGMA: q = A p
     const double *b;        // RESID
     const double *x;        // RESID
     double *r;              // RESID: r = b - A x
@@ -72,11 +70,60 @@ __device__ __forceinline__ T csr_load(const T *p) {
 #endif
 }
 
-// The one place the updated direction is formed, so that the value gathered
-// by a neighbouring row and the value stored for the own row are identical.
+// The updated direction p_new = z + beta p_old of row i (one rounding).
 __device__ __forceinline__ double dir_value(double beta, const double *pold, const double *z, int i) {
     return __builtin_fma(beta, pold[i], z[i]);
 }
+
+// What a mode gathers for a column, the own-row value it needs, and what it
+// stores and accumulates once a row's product is known.  Shared by both
+// schedules below.
+template <int MODE>
+struct SpmvMode_ {
+    const SpmvArgs &a;
+    double invb = 0.0;
+    const double *src = nullptr;
+    const double *pnew = nullptr;
+
+    __device__ __forceinline__ SpmvMode_(const SpmvArgs &args, const PcgState *st) : a(args) {
+        if (MODE == SPMV_SIGMA) {
+            pnew = (st->it & 1) ? a.p0 : a.p1;
+            src = pnew;
+        }
+        if (MODE == SPMV_RESID) src = a.x;
+        if (MODE == SPMV_LANCZOS) {
+            invb = a.ls->invb;
+            src = a.zt;
+        }
+    }
+    __device__ __forceinline__ double gather(int col) const {
+        if (MODE == SPMV_LANCZOS) return src[col] * invb;
+        return src[col];
+    }
+    __device__ __forceinline__ double own(int i) const {
+        if (MODE == SPMV_SIGMA) return pnew[i];
+        if (MODE == SPMV_RESID) return a.b[i];
+        return a.zt[i] * invb;
+    }
+    // row i with own value ov and product acc = (A s)_i
+    __device__ __forceinline__ void finish(int i, double ov, double acc, double &d0, double &d1) const {
+        if (MODE == SPMV_SIGMA) {
+            a.q[i] = acc;
+            d0 += ov * acc;
+        } else if (MODE == SPMV_RESID) {
+            const double rv = ov - acc;
+            a.r[i] = rv;
+            d0 += ov * ov;
+            d1 += rv * rv;
+        } else {
+            const size_t at = (size_t)a.ls->j * a.ld + i;
+            a.V[at] = ov;
+            if (a.has_m) a.U[at] = a.rt[i] * invb;
+            a.w[i] = acc;
+            d0 += ov * acc;
+        }
+    }
+};
 
 // Rows [r0, r1) of the product in the given mode; accumulates this thread's
 // share of the mode's dot products into d0, d1.  `st` is the state of the
@@ -91,27 +138,8 @@ __device__ __forceinline__ void spmv_rows(const SpmvArgs &a, const PcgState *st,
     constexpr int U = spmv_rows_per_group(GS);
     constexpr int RWG = kWG / GS;
     const int tid = threadIdx.x, sub = tid & (GS - 1), grp = tid / GS;
-
-    double beta = 0.0, invb = 0.0;
-    const double *pold = nullptr, *src = nullptr;
-    double *pnew = nullptr;
-    if (MODE == SPMV_DIR || MODE == SPMV_SIGMA) {
-        const int it = st->it;
-        pold = (it & 1) ? a.p1 : a.p0;
-        pnew = (it & 1) ? a.p0 : a.p1;
-        beta = st->beta;
-    }
-    if (MODE == SPMV_SIGMA) src = pnew;
-    if (MODE == SPMV_RESID) src = a.x;
-    if (MODE == SPMV_LANCZOS) {
-        invb = a.ls->invb;
-        src = a.zt;
-    }
-    auto gather = [&](int col) -> double {
-        if (MODE == SPMV_DIR) return dir_value(beta, pold, a.z, col);
-        if (MODE == SPMV_LANCZOS) return src[col] * invb;
-        return src[col];
-    };
+    const SpmvMode_<MODE> m(a, st);
+    auto gather = [&](int col) -> double { return m.gather(col); };
 
     // All loads of a step are unconditional (out-of-range rows and lanes use
     // clamped, in-bounds indices and are masked afterwards), so the compiler
@@ -130,10 +158,7 @@ __device__ __forceinline__ void spmv_rows(const SpmvArgs &a, const PcgState *st,
             const bool ok = row[u] < r1;
             kb[u] = ok ? b0 : 0;
             ke[u] = ok ? e0 : 0;
-            if (MODE == SPMV_DIR) own[u] = dir_value(beta, pold, a.z, rc);
-            else if (MODE == SPMV_SIGMA) own[u] = pnew[rc];
-            else if (MODE == SPMV_RESID) own[u] = a.b[rc];
-            else own[u] = a.zt[rc] * invb;
+            own[u] = m.own(rc);
         }
         constexpr int NP = spmv_passes(GS);
         int col[U][NP];
@@ -170,28 +195,61 @@ __device__ __forceinline__ void spmv_rows(const SpmvArgs &a, const PcgState *st,
         for (int u = 0; u < U; ++u) {
             const int i = row[u];
             if (i >= r1 || sub != 0) continue;
-            if (MODE == SPMV_DIR) {
-                pnew[i] = own[u];
-                a.q[i] = acc[u];
-                d0 += own[u] * acc[u];
-            } else if (MODE == SPMV_SIGMA) {
-                a.q[i] = acc[u];
-                d0 += own[u] * acc[u];
-            } else if (MODE == SPMV_RESID) {
-                const double rv = own[u] - acc[u];
-                a.r[i] = rv;
-                d0 += own[u] * own[u];
-                d1 += rv * rv;
-            } else {
-                const size_t at = (size_t)a.ls->j * a.ld + i;
-                a.V[at] = own[u];
-                if (a.has_m) a.U[at] = a.rt[i] * invb;
-                a.w[i] = acc[u];
-                d0 += own[u] * acc[u];
-            }
+            m.finish(i, own[u], acc[u], d0, d1);
         }
     }
+}
 
+// Row-block streaming schedule for short rows: a workgroup takes blocks of
+// kStreamRows consecutive rows; the block's CSR entries are read fully
+// coalesced (thread t takes entries t, t + 256, ...), multiplied by their
+// gathered vector entries and staged in LDS, kStreamCap at a time; then
+// thread t sums the products of row t of the block in entry order.  Every
+// load of a stage is issued before the first is used.
+#ifndef BJP_STREAM_CAP
+#define BJP_STREAM_CAP 1024
+#endif
+constexpr int kStreamRows = kWG;
+constexpr int kStreamCap = BJP_STREAM_CAP;
+constexpr int kStreamPer = kStreamCap / kWG;
+
+template <int MODE>
+__device__ __forceinline__ void spmv_stream_rows(const SpmvArgs &a, const PcgState *st, int r0, int r1,
+                                                 double &d0, double &d1) {
+    __shared__ double prod[kStreamCap];
+    const int tid = threadIdx.x;
+    const SpmvMode_<MODE> m(a, st);
+    const int32_t *__restrict__ rp = a.rp;
+    const int32_t *__restrict__ ci = a.ci;
+    const double *__restrict__ val = a.val;
+    for (int b0 = r0; b0 < r1; b0 += kStreamRows) {
+        const int b1 = min(b0 + kStreamRows, r1);
+        const int i = b0 + tid;
+        const int ic = min(i, b1 - 1);
+        const int kb = rp[ic], ke = rp[ic + 1];
+        const int base = rp[b0], end = rp[b1];
+        const double ov = m.own(ic);
+        double acc = 0.0;
+        for (int c0 = base; c0 < end; c0 += kStreamCap) {
+            const int c1 = min(c0 + kStreamCap, end);
+            int col[kStreamPer];
+            double vv[kStreamPer];
+#pragma unroll
+            for (int j = 0; j < kStreamPer; ++j) {
+                const int k = c0 + j * kWG + tid;
+                const int kc = k < c1 ? k : c0;
+                col[j] = csr_load(ci + kc);
+                vv[j] = csr_load(val + kc);
+            }
+#pragma unroll
+            for (int j = 0; j < kStreamPer; ++j) prod[j * kWG + tid] = vv[j] * m.gather(col[j]);
+            __syncthreads();
+            const int lo = max(kb, c0), hi = min(ke, c1);
+            for (int k = lo; k < hi; ++k) acc += prod[k - c0];
+            __syncthreads();
+        }
+        if (i < b1) m.finish(i, ov, acc, d0, d1);
+    }
 }
 
 template <int GS, int MODE>
@@ -210,17 +268,54 @@ __global__ __launch_bounds__(kWG) void k_spmv(SpmvArgs a) {
     block_partial<2>(v, a.partials);
 }
 
-// p_new = z + beta p_old for every row (the separate direction update used
-// when the gathers of SPMV_DIR would be uncached random accesses).
-__global__ __launch_bounds__(kWG) void k_direction(PcgState *st, const double *z, double *p0,
+template <int MODE>
+__global__ __launch_bounds__(kWG) void k_spmv_stream(SpmvArgs a) {
+    if (MODE == SPMV_LANCZOS) {
+        if (a.ls->done) return;
+    } else if (!(MODE == SPMV_RESID && a.resid_phase == 1)) {
+        if (a.st->done) return;
+    }
+    const int c = xcd_chunk(blockIdx.x, gridDim.x);
+    const int r0 = c * a.chunk;
+    const int r1 = min(r0 + a.chunk, a.n);
+    double d0 = 0.0, d1 = 0.0;
+    spmv_stream_rows<MODE>(a, a.st, r0, r1, d0, d1);
+    const double v[2] = {d0, d1};
+    block_partial<2>(v, a.partials);
+}
+
+// p_new = z + beta p_old, with the deferred update decision as prologue:
+// every workgroup takes it from the partials of the block-inverse
+// application (r^T z, r^T r) and the state src; workgroup 0 records the new
+// state at dst.  The z and p_old of the first kDirRows rows of each thread are
+// loaded before the decision (which buffer is p_old follows from src alone).
+constexpr int kDirRows = 4;
+
+template <int OP>
+__global__ __launch_bounds__(kWG) void k_direction(const PcgState *src, PcgState *dst, const double *partials,
+                                                   int nparts, double *hist, const double *z, double *p0,
                                                    double *p1, int n) {
-    if (st->done) return;
-    const int it = st->it;
-    const double *pold = (it & 1) ? p1 : p0;
-    double *pnew = (it & 1) ? p0 : p1;
-    const double beta = st->beta;
-    for (int i = blockIdx.x * kWG + threadIdx.x; i < n; i += gridDim.x * kWG)
-        pnew[i] = dir_value(beta, pold, z, i);
+    const int it_next = src->it + (src->pending ? 1 : 0);
+    const double *pold = (it_next & 1) ? p1 : p0;
+    double *pnew = (it_next & 1) ? p0 : p1;
+    const int stride = gridDim.x * kWG;
+    const int i0 = blockIdx.x * kWG + threadIdx.x;
+    double zv[kDirRows], pv[kDirRows];
+#pragma unroll
+    for (int j = 0; j < kDirRows; ++j) {
+        const int i = min(i0 + j * stride, n - 1);
+        zv[j] = z[i];
+        pv[j] = pold[i];
+    }
+    const PcgState L = shared_decide<OP>(src, dst, partials, nparts, hist);
+    if (L.done) return;
+    const double beta = L.beta;
+#pragma unroll
+    for (int j = 0; j < kDirRows; ++j) {
+        const int i = i0 + j * stride;
+        if (i < n) pnew[i] = __builtin_fma(beta, pv[j], zv[j]);
+    }
+    for (int i = i0 + kDirRows * stride; i < n; i += stride) pnew[i] = dir_value(beta, pold, z, i);
 }
 
 }  // namespace bjp
