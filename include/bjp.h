@@ -233,7 +233,9 @@ typedef struct {
     int32_t lanes;               /* lanes per CSR row: 0 = auto, else a power of two <= 64 */
     int32_t tile_rows;           /* rows per SpMV tile: 0 = auto (2048), else >= 256 */
     int32_t check_every;         /* iterations between convergence polls (default 16) */
-    int32_t pad;
+    int32_t eager;               /* 0: the check_every iterations between polls are
+                                    captured once into a hipGraph and replayed;
+                                    1: every kernel is launched from the host       */
 } bjp_batch_opts_t;
 
 /* Per-system result (same layout as the device record the solver writes). */

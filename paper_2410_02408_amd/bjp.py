@@ -366,7 +366,7 @@ class BatchPrecondT(C.Structure):
 class BatchOptsT(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("max_replacements", C.c_int32),
                 ("lanes", C.c_int32), ("tile_rows", C.c_int32), ("check_every", C.c_int32),
-                ("pad", C.c_int32)]
+                ("eager", C.c_int32)]
 
 
 class SystemInfoT(C.Structure):
@@ -470,8 +470,11 @@ class BatchInfo:
 
 def batch_pcg_solve(B: Batch, M: BatchPrecond, b, tol: float = 1e-10, max_iter: int = 0,
                     lanes: int = 0, tile_rows: int = 0, check_every: int = 0,
-                    out: torch.Tensor | None = None, workspace: torch.Tensor | None = None):
-    """bjp_batch_pcg_solve: every system advances in the same launches."""
+                    out: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
+                    graph: bool = True):
+    """bjp_batch_pcg_solve: every system advances in the same launches (the
+    iterations between polls replayed from a captured hipGraph unless
+    graph=False)."""
     L = _load_batch(load())
     dev = B.A.device
     b = _vec(b, dev)
@@ -483,7 +486,7 @@ def batch_pcg_solve(B: Batch, M: BatchPrecond, b, tol: float = 1e-10, max_iter: 
         if st:
             raise BjpError(st, "bjp_batch_pcg_workspace")
         workspace = _workspace(n.value, dev)
-    opts = BatchOptsT(tol, int(max_iter), 0, int(lanes), int(tile_rows), int(check_every), 0)
+    opts = BatchOptsT(tol, int(max_iter), 0, int(lanes), int(tile_rows), int(check_every), 0 if graph else 1)
     info = BatchInfoT()
     per = (SystemInfoT * B.num_systems)()
     st = L.bjp_batch_pcg_solve(C.byref(csr), C.byref(bs), C.byref(M.handle), _ptr(b), _ptr(x),

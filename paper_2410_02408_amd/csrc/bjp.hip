@@ -351,6 +351,18 @@ int spmv_schedule(int opt, const bjp_csr_t *A) {
 // ---------------------------------------------------------------------------
 // batches
 // ---------------------------------------------------------------------------
+// Owner of the batch solver's captured graph and capture stream.
+struct GraphGuard {
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec = nullptr;
+    GraphGuard() = default;
+    GraphGuard(const GraphGuard &) = delete;
+    GraphGuard &operator=(const GraphGuard &) = delete;
+    ~GraphGuard() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
 struct BatchPlan {
     std::vector<SysInfo> sys;
     std::vector<int32_t> off;        // per system: nblocks+1 global row offsets
@@ -473,6 +485,29 @@ void launch_apply_tiles_t(int G, int grid, const ApplyArgs &a, const TileSpan &t
         default: hipLaunchKernelGGL((k_apply_tiles<64, TS, MODE>), dim3(grid), dim3(kWG), 0, s, a, t); break;
     }
 }
+
+// Two pinned host slots per host thread for the solver's overlapped polls
+// (allocated on first use, kept for the life of the thread's process).
+PcgState *pinned_states() {
+    static thread_local PcgState *p = nullptr;
+    if (!p) {
+        void *q = nullptr;
+        if (hipHostMalloc(&q, 2 * sizeof(PcgState), hipHostMallocDefault) != hipSuccess) return nullptr;
+        p = static_cast<PcgState *>(q);
+    }
+    return p;
+}
+
+struct EventPair {
+    hipEvent_t e[2] = {nullptr, nullptr};
+    EventPair() = default;
+    EventPair(const EventPair &) = delete;
+    EventPair &operator=(const EventPair &) = delete;
+    ~EventPair() {
+        for (hipEvent_t v : e)
+            if (v) (void)hipEventDestroy(v);
+    }
+};
 
 }  // namespace
 
@@ -748,27 +783,53 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
     finish<FIN_RESID_START>(fa, Ls.grid, stream);
     start_direction();
 
+    // Polls overlap the iterations: the next batch is launched before the
+    // state copied after the previous batch is examined, so the GPU does not
+    // wait for the host.  Iterations launched after convergence return at
+    // once.  Batch sizes follow the observed convergence rate.
+    PcgState *hs = pinned_states();
+    if (!hs) return fail(BJP_EHIP);
+    EventPair ev;
+    HIP_TRY(hipEventCreateWithFlags(&ev.e[0], hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&ev.e[1], hipEventDisableTiming));
+    auto post = [&](int slot) -> int {
+        commit();
+        HIP_TRY(hipMemcpyAsync(&hs[slot], st, sizeof(PcgState), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipEventRecord(ev.e[slot], stream));
+        return BJP_OK;
+    };
+    auto take = [&](int slot, PcgState &out) -> int {
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipEventSynchronize(ev.e[slot]));
+        out = hs[slot];
+        return BJP_OK;
+    };
+
     PcgState h{};
-    int launched = 0, replacements = 0, polls = 0, status = BJP_OK;
-    int chunk = o.check_every;
+    int replacements = 0, polls = 0, status = BJP_OK;
+    int cur = 0, inflight = o.check_every;
     double prev_rel = -1.0;
     int prev_it = 0;
+    for (int c = 0; c < inflight; ++c) iteration();
+    if ((s = post(0)) != BJP_OK) return fail(s);
+    int next = o.check_every;
     for (;;) {
-        for (int c = 0; c < chunk; ++c) iteration();
-        launched += chunk;
-        if ((s = read_state(h)) != BJP_OK) return fail(s);
+        for (int c = 0; c < next; ++c) iteration();
+        if ((s = post(cur ^ 1)) != BJP_OK) return fail(s);
+        const int launched_after = next;
+        if ((s = take(cur, h)) != BJP_OK) return fail(s);
         ++polls;
+        cur ^= 1;
         if (!h.done) {
-            // size the next batch from the observed convergence rate
-            int next = o.check_every;
+            // size the batch after the one in flight from the convergence rate
+            next = o.check_every;
             if (prev_rel > 0.0 && h.relres > 0.0 && h.it > prev_it && h.relres < prev_rel) {
                 const double rate = std::log(h.relres / prev_rel) / (h.it - prev_it);
-                const double remain = std::log(o.tol / h.relres) / rate;
+                const double remain = std::log(o.tol / h.relres) / rate - launched_after;
                 if (remain < next) next = std::max(1, (int)std::ceil(remain) + 1);
             }
             prev_rel = h.relres;
             prev_it = h.it;
-            chunk = next;
             continue;
         }
         if (h.status != BJP_OK || h.zero_rhs) break;
@@ -785,7 +846,10 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
         ++replacements;  // r now holds b - A x: restart the direction from it
         hipLaunchKernelGGL(k_pcg_restart, dim3(1), dim3(64), 0, stream, st);
         start_direction();
-        chunk = o.check_every;
+        for (int c = 0; c < o.check_every; ++c) iteration();
+        cur = 0;
+        if ((s = post(0)) != BJP_OK) return fail(s);
+        next = o.check_every;
         prev_rel = -1.0;
     }
     if (status == BJP_OK) status = h.status;
@@ -1148,26 +1212,55 @@ int bjp_batch_pcg_solve(const bjp_csr_t *A, const bjp_batch_t *B, const bjp_batc
     fa.st = states;
     fa.partials = partials;
 
+    // `ls` is the stream the iteration kernels go to: the caller's stream, or
+    // the capture stream while the graph is recorded
+    hipStream_t ls = stream;
     auto apply_all = [&](auto mode_tag) {
         constexpr int MODE = decltype(mode_tag)::value;
         for (size_t c = 0; c < T.cls_g.size(); ++c) {
             const TileSpan span{tiles + nrt, T.cls_begin[c], T.cls_end[c], npt,
                                 static_cast<const SysInfo *>(M->systems)};
             const int grid = round8(T.cls_end[c] - T.cls_begin[c]);
-            if (M->precision == BJP_FP32_STORE) launch_apply_tiles_t<float, MODE>(T.cls_g[c], grid, aa, span, stream);
-            else launch_apply_tiles_t<double, MODE>(T.cls_g[c], grid, aa, span, stream);
+            if (M->precision == BJP_FP32_STORE) launch_apply_tiles_t<float, MODE>(T.cls_g[c], grid, aa, span, ls);
+            else launch_apply_tiles_t<double, MODE>(T.cls_g[c], grid, aa, span, ls);
         }
     };
     auto start_direction = [&]() {
         apply_all(std::integral_constant<int, APPLY_INIT>{});
-        hipLaunchKernelGGL(k_finish_sys<FIN_PCG_START>, dim3(S), dim3(kWG), 0, stream, fa, ptb, pte, npt);
+        hipLaunchKernelGGL(k_finish_sys<FIN_PCG_START>, dim3(S), dim3(kWG), 0, ls, fa, ptb, pte, npt);
     };
     auto iteration = [&]() {
-        hipLaunchKernelGGL(k_direction_tiles, dim3(rgrid), dim3(kWG), 0, stream, states, z, p0, p1, rows);
-        launch_spmv_tiles<SPMV_SIGMA>(gs, rgrid, sa, rows, stream);
-        hipLaunchKernelGGL(k_finish_sys<FIN_SIGMA>, dim3(S), dim3(kWG), 0, stream, fa, rtb, rte, nrt);
+        hipLaunchKernelGGL(k_direction_tiles, dim3(rgrid), dim3(kWG), 0, ls, states, z, p0, p1, rows);
+        launch_spmv_tiles<SPMV_SIGMA>(gs, rgrid, sa, rows, ls);
+        hipLaunchKernelGGL(k_finish_sys<FIN_SIGMA>, dim3(S), dim3(kWG), 0, ls, fa, rtb, rte, nrt);
         apply_all(std::integral_constant<int, APPLY_UPDATE>{});
-        hipLaunchKernelGGL(k_finish_sys<FIN_PCG_UPDATE>, dim3(S), dim3(kWG), 0, stream, fa, ptb, pte, npt);
+        hipLaunchKernelGGL(k_finish_sys<FIN_PCG_UPDATE>, dim3(S), dim3(kWG), 0, ls, fa, ptb, pte, npt);
+    };
+    // The check_every iterations between polls are recorded once into a graph
+    // (on a private stream: the caller's may be the null stream, which cannot
+    // capture) and replayed on the caller's stream.  Every kernel reads its
+    // scalars from the device state, so one recording serves every replay.
+    // The graph holds kernel nodes only.
+    GraphGuard gg;
+    if (!o.eager) {
+        HIP_TRY(hipStreamCreateWithFlags(&gg.cap, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(gg.cap, hipStreamCaptureModeThreadLocal));
+        ls = gg.cap;
+        for (int c = 0; c < o.check_every; ++c) iteration();
+        ls = stream;
+        hipGraph_t g = nullptr;
+        HIP_TRY(hipStreamEndCapture(gg.cap, &g));
+        const hipError_t e = hipGraphInstantiate(&gg.exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIP_TRY(e);
+    }
+    auto iterations = [&]() -> int {
+        if (gg.exec) {
+            HIP_TRY(hipGraphLaunch(gg.exec, stream));
+        } else {
+            for (int c = 0; c < o.check_every; ++c) iteration();
+        }
+        return BJP_OK;
     };
     std::vector<PcgState> h(S);
     auto read_states = [&]() -> int {
@@ -1186,7 +1279,7 @@ int bjp_batch_pcg_solve(const bjp_csr_t *A, const bjp_batch_t *B, const bjp_batc
     for (;;) {
         int active = 0;
         for (;;) {
-            for (int c = 0; c < o.check_every; ++c) iteration();
+            if ((st = iterations()) != BJP_OK) return fail(st);
             if ((st = read_states()) != BJP_OK) return fail(st);
             active = 0;
             for (int s = 0; s < S; ++s) active += h[s].done ? 0 : 1;

@@ -85,3 +85,24 @@ def test_batch_autotune_picks_a_candidate(gpu, tmp_path, monkeypatch):
     assert cfg2 == cfg and t2 is None
     x, info = gpu.batch_pcg_solve(B, M, np.concatenate(rhs), **cfg)
     assert info.status == "OK"
+
+
+def test_batch_graph_replays_match_eager(gpu):
+    """The captured-graph iterations reproduce the eagerly launched ones bit
+    for bit: several replays per solve (polls every 3 iterations, with the
+    host reading the states between replays), over two solves in a row."""
+    mats, nbs, rhs = small_batch(10, seed=11)
+    B = gpu.Batch.from_systems(mats, nbs, DEV)
+    M = gpu.batch_precondition(B)
+    b = np.concatenate(rhs)
+    xe, ie = gpu.batch_pcg_solve(B, M, b, check_every=3, graph=False)
+    ws = None
+    for _ in range(2):
+        xg, ig = gpu.batch_pcg_solve(B, M, b, check_every=3, graph=True, workspace=ws)
+        torch.cuda.synchronize()
+        assert torch.equal(xg, xe)
+        assert np.array_equal(ig.per_system["iterations"], ie.per_system["iterations"])
+        assert np.array_equal(ig.per_system["rel_res_true"], ie.per_system["rel_res_true"])
+        assert ig.status == ie.status == "OK"
+        xe2 = torch.empty_like(xe).copy_(xe)   # eager device work between the solves
+        assert torch.equal(xe2, xe)
