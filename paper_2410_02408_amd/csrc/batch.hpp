@@ -55,7 +55,7 @@ __global__ __launch_bounds__(kWG) void k_spmv_tiles(SpmvArgs a, TileSpan ts) {
         const Tile tl = ts.tiles[t];
         const PcgState *st = a.st + tl.s;
         const bool run = (MODE == SPMV_RESID && a.resid_phase == 1) || !st->done;
-        if (run) spmv_rows<GS, MODE>(a, st, tl.a0, tl.a1, d0, d1);
+        if (run) spmv_rows<GS, MODE>(a, st->it, tl.a0, tl.a1, d0, d1);
     }
     const double v[2] = {d0, d1};
     block_partial_at<2>(v, a.partials, ts.stride, t < ts.end ? t : -1);

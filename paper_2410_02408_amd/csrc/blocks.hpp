@@ -10,9 +10,11 @@
 // k = 0 .. G/2-1 are full rows of 64 scalars (one per lane of the packet), and
 // for n = G the self-paired diagonal k = G/2 is a half row of 32 scalars.  A
 // packet therefore holds 64*(G/2) + 32 scalars = P * G(G+1)/2, exactly the
-// packed-triangle size, and lane l of the wave reads element l of every row:
-// each row is one fully coalesced 512-byte (FP64) load.  Blocks shorter than
-// G use rows 0 .. floor(n/2) and zeros elsewhere.
+// packed-triangle size.  Full diagonals are stored in pairs, interleaved per
+// lane (diag_index): lane l reads d_k[l] and d_{k+1}[l] with one 16-byte load,
+// so a wave's load covers 1 KB contiguously and a 64-row packet takes 17 loads
+// per lane (16 pairs and the half row).  Blocks shorter than G use diagonals
+// 0 .. floor(n/2) and zeros elsewhere.
 //
 // Application in lane i of a group:
 //     z_i = sum_k d_k[i] r_{(i+k) mod n}              (upper part, own diagonal)
@@ -28,6 +30,16 @@
 namespace bjp {
 
 __host__ __device__ constexpr int packet_elems(int G) { return G == 1 ? 64 : 64 * (G / 2) + 32; }
+
+// Position in a packet of d_k for lane l = g*G + i (group g, row i): pairs
+// (k, k+1), k even, interleaved per lane; an unpaired last full diagonal (G/2
+// odd: G = 2) as a plain row; the half diagonal k = G/2 after the full ones.
+__host__ __device__ constexpr int diag_index(int G, int k, int lane) {
+    const int K = G / 2, Kp = K & ~1;
+    return k < Kp ? (k >> 1) * 128 + 2 * lane + (k & 1)
+                  : (k < K || K == 0 ? Kp * 64 + (k - Kp) * 64 + lane
+                                     : K * 64 + (lane / G) * K + ((lane % G) & (K - 1)));
+}
 
 // ---------------------------------------------------------------------------
 // Build: one wave per packet.  LDS holds the P tiles (padded stride G+1).
@@ -120,12 +132,12 @@ __global__ __launch_bounds__(64) void k_setup(SetupArgs a) {
             if (jj >= n) jj -= n;
             v = (i >= jj) ? Tg[i][jj] : Tg[jj][i];
         }
-        D[k * 64 + lane] = (TS)v;
+        D[diag_index(G, k, lane)] = (TS)v;
     }
     if (G > 1 && i < G / 2) {
         double v = 0.0;
         if (n == G) v = Tg[i + G / 2][i];
-        D[(G / 2) * 64 + g * (G / 2) + i] = (TS)v;
+        D[diag_index(G, G / 2, lane)] = (TS)v;
     }
 }
 
@@ -151,12 +163,23 @@ __device__ __forceinline__ TS tile_load(const TS *p) {
 // One packet, one wave: lane i of group g holds row i of block g.
 // packet_load issues the K + 1 loads of this lane's diagonal entries (the
 // half row counts as diagonal K = G/2); packet_product forms z_i from them.
+template <typename TS>
+struct Pair {
+    typedef TS type __attribute__((ext_vector_type(2)));
+};
+
 template <int G, typename TS>
 __device__ __forceinline__ void packet_load(const TS *__restrict__ D, int lane, int g, int i, TS (&dv)[G / 2 + 1]) {
-    constexpr int K = G / 2;
-    dv[0] = tile_load(D + lane);
+    constexpr int K = G / 2, Kp = K & ~1;
+    typedef typename Pair<TS>::type TS2;
 #pragma unroll
-    for (int k = 1; k <= K; ++k) dv[k] = tile_load(k < K ? D + k * 64 + lane : D + K * 64 + g * K + (i & (K - 1)));
+    for (int k = 0; k < Kp; k += 2) {
+        const TS2 v = tile_load(reinterpret_cast<const TS2 *>(D + diag_index(G, k, lane)));
+        dv[k] = v.x;
+        dv[k + 1] = v.y;
+    }
+#pragma unroll
+    for (int k = Kp; k <= K; ++k) dv[k] = tile_load(D + diag_index(G, k, lane));
 }
 
 // Whole-wave rotations by one lane (DPP): kDppWaveRor1 gives lane i the

@@ -41,7 +41,7 @@ struct SpmvArgs {
     const int32_t *rp, *ci;
     const double *val;
     PcgState *st;
-    double *p0, *p1;        // SIGMA: direction ping-pong, selected by st->it
+    double *p0, *p1;        // SIGMA: direction ping-pong, selected by the iteration count
     double *q;              // SIGMA: q = A p
     const double *b;        // RESID
     const double *x;        // RESID
@@ -85,9 +85,10 @@ struct SpmvMode_ {
     const double *src = nullptr;
     const double *pnew = nullptr;
 
-    __device__ __forceinline__ SpmvMode_(const SpmvArgs &args, const PcgState *st) : a(args) {
+    // it: iteration count of the system's state (selects the direction buffer)
+    __device__ __forceinline__ SpmvMode_(const SpmvArgs &args, int it) : a(args) {
         if (MODE == SPMV_SIGMA) {
-            pnew = (st->it & 1) ? a.p0 : a.p1;
+            pnew = (it & 1) ? a.p0 : a.p1;
             src = pnew;
         }
         if (MODE == SPMV_RESID) src = a.x;
@@ -129,8 +130,7 @@ struct SpmvMode_ {
 // share of the mode's dot products into d0, d1.  `st` is the state of the
 // system the rows belong to.  Called by every thread of the workgroup.
 template <int GS, int MODE>
-__device__ __forceinline__ void spmv_rows(const SpmvArgs &a, const PcgState *st, int r0, int r1, double &d0,
-                                          double &d1) {
+__device__ __forceinline__ void spmv_rows(const SpmvArgs &a, int it, int r0, int r1, double &d0, double &d1) {
     // U rows per lane group are processed together so that several
     // row_ptr -> col -> gather chains are in flight per lane.  The CSR
     // arrays must hold at least one entry (callers pass a zero entry for an
@@ -138,7 +138,7 @@ __device__ __forceinline__ void spmv_rows(const SpmvArgs &a, const PcgState *st,
     constexpr int U = spmv_rows_per_group(GS);
     constexpr int RWG = kWG / GS;
     const int tid = threadIdx.x, sub = tid & (GS - 1), grp = tid / GS;
-    const SpmvMode_<MODE> m(a, st);
+    const SpmvMode_<MODE> m(a, it);
     auto gather = [&](int col) -> double { return m.gather(col); };
 
     // All loads of a step are unconditional (out-of-range rows and lanes use
@@ -214,11 +214,11 @@ constexpr int kStreamCap = BJP_STREAM_CAP;
 constexpr int kStreamPer = kStreamCap / kWG;
 
 template <int MODE>
-__device__ __forceinline__ void spmv_stream_rows(const SpmvArgs &a, const PcgState *st, int r0, int r1,
-                                                 double &d0, double &d1) {
+__device__ __forceinline__ void spmv_stream_rows(const SpmvArgs &a, int it, int r0, int r1, double &d0,
+                                                 double &d1) {
     __shared__ double prod[kStreamCap];
     const int tid = threadIdx.x;
-    const SpmvMode_<MODE> m(a, st);
+    const SpmvMode_<MODE> m(a, it);
     const int32_t *__restrict__ rp = a.rp;
     const int32_t *__restrict__ ci = a.ci;
     const double *__restrict__ val = a.val;
@@ -252,34 +252,39 @@ __device__ __forceinline__ void spmv_stream_rows(const SpmvArgs &a, const PcgSta
     }
 }
 
+// Whether the launch has work, and the iteration count it needs.
+template <int MODE>
+__device__ __forceinline__ bool spmv_state(const SpmvArgs &a, int &it) {
+    if (MODE == SPMV_LANCZOS) return !a.ls->done;
+    if (MODE == SPMV_SIGMA) {
+        it = a.st->it;
+        return !a.st->done;
+    }
+    return a.resid_phase == 1 || !a.st->done;
+}
+
 template <int GS, int MODE>
 __global__ __launch_bounds__(kWG) void k_spmv(SpmvArgs a) {
-    if (MODE == SPMV_LANCZOS) {
-        if (a.ls->done) return;
-    } else if (!(MODE == SPMV_RESID && a.resid_phase == 1)) {
-        if (a.st->done) return;
-    }
+    int it = 0;
+    if (!spmv_state<MODE>(a, it)) return;
     const int c = xcd_chunk(blockIdx.x, gridDim.x);
     const int r0 = c * a.chunk;
     const int r1 = min(r0 + a.chunk, a.n);
     double d0 = 0.0, d1 = 0.0;
-    spmv_rows<GS, MODE>(a, a.st, r0, r1, d0, d1);
+    spmv_rows<GS, MODE>(a, it, r0, r1, d0, d1);
     const double v[2] = {d0, d1};
     block_partial<2>(v, a.partials);
 }
 
 template <int MODE>
 __global__ __launch_bounds__(kWG) void k_spmv_stream(SpmvArgs a) {
-    if (MODE == SPMV_LANCZOS) {
-        if (a.ls->done) return;
-    } else if (!(MODE == SPMV_RESID && a.resid_phase == 1)) {
-        if (a.st->done) return;
-    }
+    int it = 0;
+    if (!spmv_state<MODE>(a, it)) return;
     const int c = xcd_chunk(blockIdx.x, gridDim.x);
     const int r0 = c * a.chunk;
     const int r1 = min(r0 + a.chunk, a.n);
     double d0 = 0.0, d1 = 0.0;
-    spmv_stream_rows<MODE>(a, a.st, r0, r1, d0, d1);
+    spmv_stream_rows<MODE>(a, it, r0, r1, d0, d1);
     const double v[2] = {d0, d1};
     block_partial<2>(v, a.partials);
 }
@@ -289,7 +294,10 @@ __global__ __launch_bounds__(kWG) void k_spmv_stream(SpmvArgs a) {
 // application (r^T z, r^T r) and the state src; workgroup 0 records the new
 // state at dst.  The z and p_old of the first kDirRows rows of each thread are
 // loaded before the decision (which buffer is p_old follows from src alone).
-constexpr int kDirRows = 4;
+#ifndef BJP_DIR_ROWS
+#define BJP_DIR_ROWS 8
+#endif
+constexpr int kDirRows = BJP_DIR_ROWS;
 
 template <int OP>
 __global__ __launch_bounds__(kWG) void k_direction(const PcgState *src, PcgState *dst, const double *partials,

@@ -25,6 +25,18 @@ def dev(A):
     return bjp.DeviceCsr.from_host(A, DEV)
 
 
+def diag_pos(G, k, lane):
+    """Position of d_k[lane] in a packet: full diagonals in lane-interleaved
+    pairs, an unpaired last one as a row, then the half diagonal."""
+    K = G // 2
+    Kp = K & ~1
+    if k < Kp:
+        return (k >> 1) * 128 + 2 * lane + (k & 1)
+    if k < K or K == 0:
+        return Kp * 64 + (k - Kp) * 64 + lane
+    return K * 64 + (lane // G) * K + ((lane % G) & (K - 1))
+
+
 def decode_inverses(M, off):
     """Dense block inverses from the diagonal-packet layout (layout only)."""
     G = M.handle.group
@@ -42,10 +54,10 @@ def decode_inverses(M, off):
                 continue
             for i in range(n):
                 j = (i + k) % n
-                S[i, j] = S[j, i] = D[base + k * 64 + g * G + i]
+                S[i, j] = S[j, i] = D[base + diag_pos(G, k, g * G + i)]
         if G > 1 and n == G:
             for i in range(G // 2):
-                S[i, i + G // 2] = S[i + G // 2, i] = D[base + (G // 2) * 64 + g * (G // 2) + i]
+                S[i, i + G // 2] = S[i + G // 2, i] = D[base + diag_pos(G, G // 2, g * G + i)]
         out.append(S)
     return out
 
