@@ -230,7 +230,9 @@ typedef struct {
     double tol;                  /* default 1e-10 */
     int32_t max_iter;            /* per system, default its size */
     int32_t max_replacements;    /* default 3; < 0 means none */
-    int32_t lanes;               /* lanes per CSR row: 0 = auto, else a power of two <= 64 */
+    int32_t lanes;               /* CSR product schedule: 0 = auto, a power of two <= 64
+                                    = lanes per row, < 0 = row blocks streamed
+                                    through LDS                                      */
     int32_t tile_rows;           /* rows per SpMV tile: 0 = auto (2048), else >= 256 */
     int32_t check_every;         /* iterations between convergence polls (default 16) */
     int32_t eager;               /* 0: the check_every iterations between polls are

@@ -2,7 +2,7 @@
 
 The batched solver has two free schedule parameters: lanes per CSR row (the
 row-bundling of the SpMV: 4, 8, 16 or 32 lanes per row, i.e. 16..2 rows per
-wavefront) and rows per SpMV tile (the work of one workgroup).  ``tune_batch``
+wavefront, or -1 for row blocks streamed through LDS) and rows per SpMV tile (the work of one workgroup).  ``tune_batch``
 times every candidate on the actual batch for a short, fixed number of PCG
 iterations per system (so each candidate does the same work), keeps the
 fastest, and caches the choice in a JSON file keyed by the batch's shape
@@ -21,7 +21,7 @@ import torch
 
 from . import bjp
 
-LANES = (4, 8, 16, 32)
+LANES = (-1, 4, 8, 16, 32)
 TILE_ROWS = (1024, 2048, 4096)
 
 

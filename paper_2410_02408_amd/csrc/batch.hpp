@@ -61,6 +61,21 @@ __global__ __launch_bounds__(kWG) void k_spmv_tiles(SpmvArgs a, TileSpan ts) {
     block_partial_at<2>(v, a.partials, ts.stride, t < ts.end ? t : -1);
 }
 
+// Row-block streaming schedule over row tiles (short rows).
+template <int MODE>
+__global__ __launch_bounds__(kWG) void k_spmv_tiles_stream(SpmvArgs a, TileSpan ts) {
+    const int t = tile_of(ts);
+    double d0 = 0.0, d1 = 0.0;
+    if (t < ts.end) {
+        const Tile tl = ts.tiles[t];
+        const PcgState *st = a.st + tl.s;
+        const bool run = (MODE == SPMV_RESID && a.resid_phase == 1) || !st->done;
+        if (run) spmv_stream_rows<MODE>(a, st->it, tl.a0, tl.a1, d0, d1);
+    }
+    const double v[2] = {d0, d1};
+    block_partial_at<2>(v, a.partials, ts.stride, t < ts.end ? t : -1);
+}
+
 template <int G, typename TS, int MODE>
 __global__ __launch_bounds__(kWG) void k_apply_tiles(ApplyArgs a, TileSpan ts) {
     const int t = tile_of(ts);

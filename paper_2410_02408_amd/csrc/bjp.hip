@@ -463,6 +463,7 @@ size_t batch_tiles_bound(const BatchPlan &P, int min_tile_rows, size_t *nrt, siz
 template <int MODE>
 void launch_spmv_tiles(int gs, int grid, const SpmvArgs &a, const TileSpan &t, hipStream_t s) {
     switch (gs) {
+        case 0: hipLaunchKernelGGL((k_spmv_tiles_stream<MODE>), dim3(grid), dim3(kWG), 0, s, a, t); break;
         case 1: hipLaunchKernelGGL((k_spmv_tiles<1, MODE>), dim3(grid), dim3(kWG), 0, s, a, t); break;
         case 2: hipLaunchKernelGGL((k_spmv_tiles<2, MODE>), dim3(grid), dim3(kWG), 0, s, a, t); break;
         case 4: hipLaunchKernelGGL((k_spmv_tiles<4, MODE>), dim3(grid), dim3(kWG), 0, s, a, t); break;
@@ -1143,7 +1144,7 @@ int bjp_batch_pcg_solve(const bjp_csr_t *A, const bjp_batch_t *B, const bjp_batc
     else if (o.max_replacements < 0) o.max_replacements = 0;
     if (o.check_every <= 0) o.check_every = 16;
     const int tile_rows = o.tile_rows > 0 ? std::max(256, o.tile_rows) : 2048;
-    const int gs = o.lanes > 0 ? pow2_at_least(std::min(o.lanes, 64)) : auto_lanes(A);
+    const int gs = spmv_schedule(o.lanes, A);
 
     BatchTables T;
     make_batch_tables(P, tile_rows, T);

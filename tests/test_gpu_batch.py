@@ -14,7 +14,7 @@ def small_batch(count=12, seed=5):
     return mats, nbs, rhs
 
 
-@pytest.mark.parametrize("lanes,tile_rows", [(0, 0), (4, 256), (16, 1024), (32, 4096)])
+@pytest.mark.parametrize("lanes,tile_rows", [(0, 0), (-1, 256), (-1, 2048), (4, 256), (16, 1024), (32, 4096)])
 def test_batch_matches_oracle(gpu, orc, lanes, tile_rows):
     mats, nbs, rhs = small_batch()
     B = gpu.Batch.from_systems(mats, nbs, DEV)
