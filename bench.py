@@ -46,17 +46,23 @@ def parse():
 def apply_bytes(n: int, offsets, elem: int) -> int:
     """Algorithmic bytes of one block-apply launch inside PCG: the packed
     block inverses (sum_t n_t(n_t+1)/2 scalars), the block offsets, and the
-    vectors x, p, r, q read (32 N) and x, r, z written (24 N)."""
+    vectors q, r read (16 N) and r, z written (16 N)."""
     import numpy as np
 
     nt = np.diff(np.asarray(offsets, dtype=np.int64))
-    return int(elem * np.sum(nt * (nt + 1) // 2) + 4 * len(offsets) + 56 * n)
+    return int(elem * np.sum(nt * (nt + 1) // 2) + 4 * len(offsets) + 32 * n)
 
 
 def spmv_bytes(n: int, nnz: int) -> int:
-    """Algorithmic bytes of one fused SpMV launch: CSR (12 nnz + 4(N+1)),
-    z and p_old read (16 N), p_new and q written (16 N)."""
-    return 12 * nnz + 4 * (n + 1) + 32 * n
+    """Algorithmic bytes of one SpMV launch: CSR (12 nnz + 4(N+1)), p read
+    (8 N), q written (8 N)."""
+    return 12 * nnz + 4 * (n + 1) + 16 * n
+
+
+def direction_bytes(n: int) -> int:
+    """Algorithmic bytes of one direction update: x, p_old, z read (24 N),
+    x, p_new written (16 N)."""
+    return 40 * n
 
 
 def read_traffic(kernel_tag: str):
@@ -141,10 +147,9 @@ def mode_batch(args):
     nbv = np.array(nbs, dtype=np.int64)
     it = info.per_system["iterations"].astype(np.int64)
     msz = 4 if args.precision == "fp32" else 8
-    # per system per iteration: CSR, packed inverses, vectors (x,p,r,q,z traffic
-    # of the workgroup-phased iteration: p,z rd + p wr; p gathered, q wr;
-    # x,p,q,r rd + x,r,z wr)
-    per_it = 12 * nnz + 4 * n + msz * n * (nbv + 1) // 2 + 88 * n
+    # per system per iteration: CSR, packed inverses, vectors (direction 24 N,
+    # product 16 N, x/r update with the block application 56 N)
+    per_it = 12 * nnz + 4 * n + msz * n * (nbv + 1) // 2 + 96 * n
     total_bytes = float(np.sum(per_it * it))
     print(json.dumps({"mode": "batch", "workload": "random_spd_batch_512", "precision": args.precision,
                       "systems": len(mats), "rows_total": int(n.sum()), "nnz_total": int(nnz.sum()),
@@ -226,7 +231,7 @@ def mode_precision(args):
         x, info, ms, setup_ms, apply_us = res[prec]
         err = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
         elem = 4 if prec == "fp32" else 8
-        ab = elem * A_h.n * 33 // 2 + 56 * A_h.n
+        ab = elem * A_h.n * 33 // 2 + 32 * A_h.n
         print(json.dumps({"mode": "precision", "workload": "powerlaw_4m", "precision": prec,
                           "n": A_h.n, "nnz": A_h.nnz, "mean_nnz_row": round(float(deg.mean()), 2),
                           "max_nnz_row": int(deg.max()), "block_size": 32,
@@ -325,7 +330,7 @@ def main():
     elem = 4 if M.precision == bjp.FP32_STORE else 8
     ab = apply_bytes(W.A.n, off, elem)
     achieved = ab / (apply_avg_ms * 1e-3) / 1e9
-    B_iter = ab + spmv_bytes(W.A.n, W.A.nnz)
+    B_iter = ab + spmv_bytes(W.A.n, W.A.nnz) + direction_bytes(W.A.n)
     iter_gbs = B_iter * sum(iters) / (sum(pcg_ms) / 1e3) / 1e9
     traffic = read_traffic(f"apply_{args.workload}")
 
@@ -356,7 +361,7 @@ def main():
         "kappa_A": kA.kappa,
         "kappa_MA": kM.kappa,
         "rel_res_true": info.rel_res_true,
-        "roofline": {"bound": "hbm", "kernel": "k_apply (block inverse + x/r update)",
+        "roofline": {"bound": "hbm", "kernel": "k_apply (block inverse + r update)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_launch": ab, "avg_launch_us": round(apply_avg_ms * 1e3, 3),

@@ -107,6 +107,8 @@ __global__ void k_pcg_state_init(PcgState *st, double tol, int max_iter) {
     st->max_iter = max_iter;
     st->zero_rhs = 0;
     st->pending = 0;
+    st->xpend = 0;
+    st->pad = 0;
 }
 
 __global__ void k_pcg_restart(PcgState *st) {
@@ -743,26 +745,34 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
     };
     // One iteration is three launches, each taking the scalar decision of the
     // previous one as its prologue (no separate finish launches):
-    //   direction     update decision (rho, beta, convergence) -> st1; p = z + beta p
+    //   direction     update decision (rho, beta, convergence) -> st1;
+    //                 x += alpha p (owed by the last step); p = z + beta p
     //   product       q = A p, partials of p^T q
-    //   application   alpha = rho / p^T q -> st; x += alpha p, r -= alpha q,
-    //                 z = M^-1 r, partials of r^T z, r^T r (decision pending)
+    //   application   alpha = rho / p^T q -> st; r -= alpha q, z = M^-1 r,
+    //                 partials of r^T z, r^T r (decision pending, x update owed)
+    // Moving x += alpha p to the direction update, which reads p anyway, saves
+    // one vector pass per iteration.
     const int dir_grid = std::min(ceil_div(n, kWG * kDirRows), 2048);
     auto iteration = [&]() {
         if (M)
             hipLaunchKernelGGL((k_direction<FIN_PCG_UPDATE>), dim3(dir_grid), dim3(kWG), 0, stream, st, st1,
-                               partials_a, La.grid, o.history, z, p0, p1, n);
+                               partials_a, La.grid, o.history, z, p0, p1, x, n);
         else
             hipLaunchKernelGGL((k_direction<FIN_PCG_UPDATE_I>), dim3(dir_grid), dim3(kWG), 0, stream, st, st1,
-                               partials_a, La.grid, o.history, z, p0, p1, n);
+                               partials_a, La.grid, o.history, z, p0, p1, x, n);
         mark(BJP_KERNEL_SPMV, 0);
         launch_spmv<SPMV_SIGMA>(gs, Ls.grid, su, stream);
         mark(BJP_KERNEL_SPMV, 1);
         mark(BJP_KERNEL_APPLY, 0);
-        if (M) launch_apply<APPLY_UPDATE>(M, La.grid, au, stream);
-        else hipLaunchKernelGGL((k_rows_update<APPLY_UPDATE>), dim3(La.grid), dim3(kWG), 0, stream, au,
+        if (M) launch_apply<APPLY_STEP>(M, La.grid, au, stream);
+        else hipLaunchKernelGGL((k_rows_update<APPLY_STEP>), dim3(La.grid), dim3(kWG), 0, stream, au,
                                 n, La.chunk);
         mark(BJP_KERNEL_APPLY, 1);
+    };
+    // the x update still owed when the iterations stop (before x is read)
+    auto finish_x = [&]() {
+        hipLaunchKernelGGL(k_x_finish, dim3(fill_grid), dim3(kWG), 0, stream, st, p0, p1, x, n);
+        hipLaunchKernelGGL(k_x_finish_clear, dim3(1), dim3(64), 0, stream, st);
     };
     // before the host reads st: take a pending update decision in place
     auto commit = [&]() {
@@ -835,6 +845,7 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
         }
         if (h.status != BJP_OK || h.zero_rhs) break;
         // converged on the recursive residual: confirm with the true one
+        finish_x();
         sa.resid_phase = 1;
         launch_spmv<SPMV_RESID>(gs, Ls.grid, sa, stream);
         finish<FIN_RESID_TRUE>(fa, Ls.grid, stream);
@@ -859,6 +870,7 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
         h.relres_true = 0.0;
         HIP_TRY(hipStreamSynchronize(stream));
     } else if (status != BJP_OK) {
+        finish_x();
         sa.resid_phase = 1;
         launch_spmv<SPMV_RESID>(gs, Ls.grid, sa, stream);
         finish<FIN_RESID_TRUE>(fa, Ls.grid, stream);

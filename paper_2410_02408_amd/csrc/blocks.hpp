@@ -248,7 +248,10 @@ __device__ __forceinline__ TS packet_product(const TS (&dv)[G / 2 + 1], int g, i
     return zv;
 }
 
-enum ApplyMode { APPLY_PLAIN = 0, APPLY_INIT = 1, APPLY_UPDATE = 2, APPLY_LANCZOS = 3 };
+// UPDATE: x += alpha p, r -= alpha q, z = M^-1 r (the batched solver);
+// STEP: r -= alpha q, z = M^-1 r (the single-system solver applies the x
+// update in the next direction update).
+enum ApplyMode { APPLY_PLAIN = 0, APPLY_INIT = 1, APPLY_UPDATE = 2, APPLY_LANCZOS = 3, APPLY_STEP = 4 };
 
 struct ApplyArgs {
     int nblocks, num_packets, chunk;
@@ -296,7 +299,7 @@ __device__ __forceinline__ void apply_packets(const ApplyArgs &a, const PcgState
     // Two stages in turn: while the packet of one stage is multiplied, the
     // loads of the next packet fill the other.  Unrolled by two so that no
     // register copy (which would wait for the pending loads) is needed.
-    constexpr int NV = MODE == APPLY_UPDATE ? 4 : 1;
+    constexpr int NV = MODE == APPLY_UPDATE ? 4 : MODE == APPLY_STEP ? 2 : 1;
     constexpr int ND = G / 2 + 1;
     struct Stage {
         TS d[ND];
@@ -320,6 +323,9 @@ __device__ __forceinline__ void apply_packets(const ApplyArgs &a, const PcgState
             S.v[1] = pn[rc];
             S.v[2] = qv_[rc];
             S.v[3] = rv_[rc];
+        } else if constexpr (MODE == APPLY_STEP) {
+            S.v[0] = qv_[rc];
+            S.v[1] = rv_[rc];
         } else {
             S.v[0] = rin[rc];
         }
@@ -331,6 +337,8 @@ __device__ __forceinline__ void apply_packets(const ApplyArgs &a, const PcgState
         double rv;
         if constexpr (MODE == APPLY_UPDATE) {
             rv = act ? fma(-alpha, S.v[2], S.v[3]) : 0.0;
+        } else if constexpr (MODE == APPLY_STEP) {
+            rv = act ? fma(-alpha, S.v[0], S.v[1]) : 0.0;
         } else {
             rv = act ? S.v[0] : 0.0;
         }
@@ -338,6 +346,8 @@ __device__ __forceinline__ void apply_packets(const ApplyArgs &a, const PcgState
         if (act) {
             if constexpr (MODE == APPLY_UPDATE) {
                 xv_[row] = fma(alpha, S.v[1], S.v[0]);
+                rv_[row] = rv;
+            } else if constexpr (MODE == APPLY_STEP) {
                 rv_[row] = rv;
             }
             const double z = (double)zv;
@@ -382,7 +392,7 @@ __global__ __launch_bounds__(kWG) void k_apply(ApplyArgs a) {
     const int pk1 = min(pk0 + a.chunk, a.num_packets);
     double d0 = 0.0, d1 = 0.0;
     auto pre = [&](double &alpha) -> bool {
-        if (MODE != APPLY_UPDATE) return true;
+        if (MODE != APPLY_STEP) return true;
         const PcgState L = shared_decide<FIN_SIGMA>(a.st, a.st_out, a.dec_partials, a.dec_nparts, nullptr, true);
         alpha = L.alpha;
         return !L.done;
@@ -393,31 +403,24 @@ __global__ __launch_bounds__(kWG) void k_apply(ApplyArgs a) {
     block_partial<2>(v, a.partials);
 }
 
-// Preconditioner-free (M = I) counterpart of k_apply for PCG: z is r itself.
+// Preconditioner-free (M = I) counterpart of k_apply for PCG: z is r itself
+// (modes INIT and STEP).
 template <int MODE>
 __global__ __launch_bounds__(kWG) void k_rows_update(ApplyArgs a, int n, int chunk) {
-    PcgState L;
-    const PcgState *st = a.st;
-    if (MODE == APPLY_UPDATE) {
-        L = shared_decide<FIN_SIGMA>(a.st, a.st_out, a.dec_partials, a.dec_nparts, nullptr, true);
+    double alpha = 0.0;
+    if (MODE == APPLY_STEP) {
+        const PcgState L = shared_decide<FIN_SIGMA>(a.st, a.st_out, a.dec_partials, a.dec_nparts, nullptr, true);
         if (L.done) return;
-        st = &L;
+        alpha = L.alpha;
     } else if (a.st->done) {
         return;
     }
     const int c = xcd_chunk(blockIdx.x, gridDim.x);
     const int r0 = c * chunk, r1 = min(r0 + chunk, n);
-    double alpha = 0.0;
-    const double *pn = nullptr;
-    if (MODE == APPLY_UPDATE) {
-        alpha = st->alpha;
-        pn = ((st->it + 1) & 1) ? a.p1 : a.p0;
-    }
     double d1 = 0.0;
     for (int row = r0 + threadIdx.x; row < r1; row += kWG) {
         double rv = a.r[row];
-        if (MODE == APPLY_UPDATE) {
-            a.x[row] = fma(alpha, pn[row], a.x[row]);
+        if (MODE == APPLY_STEP) {
             rv = fma(-alpha, a.q[row], rv);
             a.r[row] = rv;
         }

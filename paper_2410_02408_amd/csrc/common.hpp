@@ -169,6 +169,9 @@ struct PcgState {
     int32_t max_iter;
     int32_t zero_rhs;  // b == 0
     int32_t pending;   // 1: the partials hold r^T z, r^T r of an update not yet decided
+    int32_t xpend;     // 1: x += alpha p of the last step is not yet applied (done with
+                       //    the next direction update, or by the solver at the end)
+    int32_t pad;
 };
 
 struct LanczosState {

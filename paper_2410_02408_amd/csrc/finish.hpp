@@ -192,9 +192,11 @@ __global__ __launch_bounds__(kWG) void k_finish_commit(FinishArgs f) {
 // identical state, which is returned; workgroup 0 records it at dst.  The
 // state is read with uniform (scalar) loads, independent of the vector loads
 // the launch may already have in flight.  dst must not be src: other
-// workgroups may still be reading src.  With mark_pending the recorded state
-// also marks the update the launch is about to form as pending (unless the
-// solve is done).  Must be called by every thread, once per launch.
+// workgroups may still be reading src.  With mark_pending (the application)
+// the recorded state also marks the update the launch is about to form as
+// pending and its x update as owed (unless the solve is done); without it (the
+// direction update) the owed x update is recorded as applied.  Must be called
+// by every thread, once per launch.
 // Field-wise copies of the solver state (whole-struct copies leave a private
 // stack object behind, which the compiler then places in LDS per thread).
 __device__ __forceinline__ PcgState load_state(const PcgState *__restrict__ s) {
@@ -212,6 +214,8 @@ __device__ __forceinline__ PcgState load_state(const PcgState *__restrict__ s) {
     L.max_iter = s->max_iter;
     L.zero_rhs = s->zero_rhs;
     L.pending = s->pending;
+    L.xpend = s->xpend;
+    L.pad = 0;
     return L;
 }
 __device__ __forceinline__ void store_state(PcgState *d, const PcgState &L) {
@@ -228,6 +232,7 @@ __device__ __forceinline__ void store_state(PcgState *d, const PcgState &L) {
     d->max_iter = L.max_iter;
     d->zero_rhs = L.zero_rhs;
     d->pending = L.pending;
+    d->xpend = L.xpend;
 }
 
 template <int OP>
@@ -258,8 +263,10 @@ __device__ __forceinline__ PcgState shared_decide(const PcgState *__restrict__ s
         f.hist = (blockIdx.x == 0 && tid == 0) ? hist : nullptr;
         finish_decide<OP>(f, &L, nullptr, out);
     }
-    if (mark_pending && !L.done) L.pending = 1;
-    if (blockIdx.x == 0 && tid == 0) store_state(dst, L);
+    PcgState R = L;
+    if (mark_pending && !L.done) R.pending = R.xpend = 1;
+    if (!mark_pending) R.xpend = 0;
+    if (blockIdx.x == 0 && tid == 0) store_state(dst, R);
     return L;
 }
 

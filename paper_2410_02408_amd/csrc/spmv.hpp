@@ -289,33 +289,50 @@ __global__ __launch_bounds__(kWG) void k_spmv_stream(SpmvArgs a) {
     block_partial<2>(v, a.partials);
 }
 
-// p_new = z + beta p_old, with the deferred update decision as prologue:
-// every workgroup takes it from the partials of the block-inverse
-// application (r^T z, r^T r) and the state src; workgroup 0 records the new
-// state at dst.  The z and p_old of the first kDirRows rows of each thread are
-// loaded before the decision (which buffer is p_old follows from src alone).
+// The direction update, with the deferred update decision as prologue: every
+// workgroup takes it from the partials of the block-inverse application
+// (r^T z, r^T r) and the state src; workgroup 0 records the new state at dst.
+// It also applies the x update owed by the last step (x += alpha p_old, with
+// that step's alpha), also when the decision ends the solve; then, unless the
+// solve is done, p_new = z + beta p_old.  The loads of the first kDirRows rows
+// of each thread are issued before the decision (which buffer is p_old
+// follows from src alone).
 #ifndef BJP_DIR_ROWS
 #define BJP_DIR_ROWS 8
 #endif
 constexpr int kDirRows = BJP_DIR_ROWS;
 
+// p_old of the direction update that follows the state s (the p of the last step).
+__device__ __forceinline__ int dir_parity(const PcgState *s) { return (s->it + (s->pending ? 1 : 0)) & 1; }
+
 template <int OP>
 __global__ __launch_bounds__(kWG) void k_direction(const PcgState *src, PcgState *dst, const double *partials,
                                                    int nparts, double *hist, const double *z, double *p0,
-                                                   double *p1, int n) {
-    const int it_next = src->it + (src->pending ? 1 : 0);
-    const double *pold = (it_next & 1) ? p1 : p0;
-    double *pnew = (it_next & 1) ? p0 : p1;
+                                                   double *p1, double *x, int n) {
+    const int par = dir_parity(src);
+    const double *pold = par ? p1 : p0;
+    double *pnew = par ? p0 : p1;
+    const bool xup = src->xpend;
+    const double alpha = src->alpha;
     const int stride = gridDim.x * kWG;
     const int i0 = blockIdx.x * kWG + threadIdx.x;
-    double zv[kDirRows], pv[kDirRows];
+    double zv[kDirRows], pv[kDirRows], xv[kDirRows];
 #pragma unroll
     for (int j = 0; j < kDirRows; ++j) {
         const int i = min(i0 + j * stride, n - 1);
         zv[j] = z[i];
         pv[j] = pold[i];
+        xv[j] = xup ? x[i] : 0.0;
     }
     const PcgState L = shared_decide<OP>(src, dst, partials, nparts, hist);
+    if (xup) {
+#pragma unroll
+        for (int j = 0; j < kDirRows; ++j) {
+            const int i = i0 + j * stride;
+            if (i < n) x[i] = __builtin_fma(alpha, pv[j], xv[j]);
+        }
+        for (int i = i0 + kDirRows * stride; i < n; i += stride) x[i] = __builtin_fma(alpha, pold[i], x[i]);
+    }
     if (L.done) return;
     const double beta = L.beta;
 #pragma unroll
@@ -324,6 +341,19 @@ __global__ __launch_bounds__(kWG) void k_direction(const PcgState *src, PcgState
         if (i < n) pnew[i] = __builtin_fma(beta, pv[j], zv[j]);
     }
     for (int i = i0 + kDirRows * stride; i < n; i += stride) pnew[i] = dir_value(beta, pold, z, i);
+}
+
+// The x update still owed at the end of a solve (no direction update follows).
+__global__ __launch_bounds__(kWG) void k_x_finish(const PcgState *st, const double *p0, const double *p1, double *x,
+                                                  int n) {
+    if (!st->xpend) return;
+    const double *pold = dir_parity(st) ? p1 : p0;
+    const double alpha = st->alpha;
+    for (int i = blockIdx.x * kWG + threadIdx.x; i < n; i += gridDim.x * kWG) x[i] = __builtin_fma(alpha, pold[i], x[i]);
+}
+
+__global__ void k_x_finish_clear(PcgState *st) {
+    if (threadIdx.x == 0) st->xpend = 0;
 }
 
 }  // namespace bjp
