@@ -21,7 +21,6 @@
 namespace bjp {
 
 constexpr int kGramRows = 8;      // rows per thread in the Gram kernels
-constexpr int kGramTile = 256;    // basis vectors reduced per LDS round
 
 enum GramPass { GRAM_FIRST = 0, GRAM_SECOND = 1, GRAM_FINAL = 2 };
 
@@ -39,6 +38,15 @@ struct GramArgs {
     double *partials;        // FINAL with M = I: per-workgroup r~^T r~
 };
 
+// Basis vectors handled per round of the Gram loops: the loads of a round are
+// issued together (clamped, in-bounds row indices; rows past the chunk are
+// masked by value, not by branches), so each thread has kGramUnroll *
+// kGramRows loads in flight.
+#ifndef BJP_GRAM_UNROLL
+#define BJP_GRAM_UNROLL 4
+#endif
+constexpr int kGramUnroll = BJP_GRAM_UNROLL;
+
 template <int PASS>
 __global__ __launch_bounds__(kWG) void k_gram(GramArgs a) {
     LanczosState *ls = a.ls;
@@ -48,52 +56,77 @@ __global__ __launch_bounds__(kWG) void k_gram(GramArgs a) {
     const int c = xcd_chunk(blockIdx.x, gridDim.x);
     const int r0 = c * a.chunk;
     const int r1 = min(r0 + a.chunk, a.n);
-    double rv[kGramRows];
-    int rows[kGramRows];
+    constexpr int Q = kGramRows, UN = kGramUnroll;
+    double rv[Q];
+    int rc[Q];
+    bool ok[Q];
 #pragma unroll
-    for (int q = 0; q < kGramRows; ++q) {
+    for (int q = 0; q < Q; ++q) {
         const int row = r0 + q * kWG + tid;
-        rows[q] = row < r1 ? row : -1;
+        ok[q] = row < r1;
+        rc[q] = min(row, a.n - 1);
         double v = 0.0;
-        if (row < r1) {
-            if (PASS == GRAM_FIRST) {
-                v = a.w[row] - ls->alpha_j * a.U[(size_t)j * a.ld + row];
-                if (j > 0) v -= ls->beta_prev * a.U[(size_t)(j - 1) * a.ld + row];
-            } else {
-                v = a.rt[row];
-            }
+        if (PASS == GRAM_FIRST) {
+            v = a.w[rc[q]] - ls->alpha_j * a.U[(size_t)j * a.ld + rc[q]];
+            if (j > 0) v -= ls->beta_prev * a.U[(size_t)(j - 1) * a.ld + rc[q]];
+        } else {
+            v = a.rt[rc[q]];
         }
-        rv[q] = v;
+        rv[q] = ok[q] ? v : 0.0;
     }
     if (PASS != GRAM_FIRST) {
-        for (int l = 0; l <= j; ++l) {
+        // r~ -= sum_l c_l u_l, l in order
+        int l = 0;
+        for (; l + UN <= j + 1; l += UN) {
+            double u[UN][Q];
+#pragma unroll
+            for (int t = 0; t < UN; ++t)
+#pragma unroll
+                for (int q = 0; q < Q; ++q) u[t][q] = a.U[(size_t)(l + t) * a.ld + rc[q]];
+#pragma unroll
+            for (int t = 0; t < UN; ++t) {
+                const double cl = a.c[l + t];
+#pragma unroll
+                for (int q = 0; q < Q; ++q) rv[q] = ok[q] ? rv[q] - cl * u[t][q] : 0.0;
+            }
+        }
+        for (; l <= j; ++l) {
             const double cl = a.c[l];
             const double *ul = a.U + (size_t)l * a.ld;
 #pragma unroll
-            for (int q = 0; q < kGramRows; ++q)
-                if (rows[q] >= 0) rv[q] -= cl * ul[rows[q]];
+            for (int q = 0; q < Q; ++q) rv[q] = ok[q] ? rv[q] - cl * ul[rc[q]] : 0.0;
         }
     }
 #pragma unroll
-    for (int q = 0; q < kGramRows; ++q)
-        if (rows[q] >= 0) a.rt[rows[q]] = rv[q];
+    for (int q = 0; q < Q; ++q)
+        if (ok[q]) a.rt[rc[q]] = rv[q];
 
     if (PASS != GRAM_FINAL) {
-        __shared__ double red[kGramTile][kWaves];
+        // partial c_l = v_l^T r~ over this workgroup's rows, l in rounds of UN
+        __shared__ double red[UN][kWaves];
         const int lane = tid & 63, wave = tid >> 6;
-        for (int l0 = 0; l0 <= j; l0 += kGramTile) {
-            const int l1 = min(l0 + kGramTile, j + 1);
-            for (int l = l0; l < l1; ++l) {
-                const double *vl = a.V + (size_t)l * a.ld;
+        for (int l0 = 0; l0 <= j; l0 += UN) {
+            double v[UN][Q];
+#pragma unroll
+            for (int t = 0; t < UN; ++t) {
+                const int l = min(l0 + t, j);
+#pragma unroll
+                for (int q = 0; q < Q; ++q) v[t][q] = a.V[(size_t)l * a.ld + rc[q]];
+            }
+            double sv[UN];
+#pragma unroll
+            for (int t = 0; t < UN; ++t) {
                 double s = 0.0;
 #pragma unroll
-                for (int q = 0; q < kGramRows; ++q)
-                    if (rows[q] >= 0) s += vl[rows[q]] * rv[q];
-                s = wave_sum(s);
-                if (lane == 0) red[l - l0][wave] = s;
+                for (int q = 0; q < Q; ++q) s += v[t][q] * rv[q];
+                sv[t] = wave_sum(s);
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int t = 0; t < UN; ++t) red[t][wave] = sv[t];
             }
             __syncthreads();
-            if (tid < l1 - l0) {
+            if (tid < UN && l0 + tid <= j) {
                 double s = 0.0;
                 for (int w = 0; w < kWaves; ++w) s += red[tid][w];
                 a.cpart[(size_t)blockIdx.x * a.ldc + l0 + tid] = s;
@@ -103,7 +136,7 @@ __global__ __launch_bounds__(kWG) void k_gram(GramArgs a) {
     } else if (!a.has_m) {
         double s = 0.0;
 #pragma unroll
-        for (int q = 0; q < kGramRows; ++q) s += rv[q] * rv[q];
+        for (int q = 0; q < Q; ++q) s += rv[q] * rv[q];
         const double v[1] = {s};
         block_partial<1>(v, a.partials);
     }
