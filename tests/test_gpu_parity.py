@@ -330,3 +330,63 @@ def test_kappa_many_steps_tiles(gpu, orc):
     ko = orc.kappa(A, w.rhs(400, 21), 300)
     assert k.steps == ko.steps
     assert abs(k.kappa - ko.kappa) <= 1e-6 * ko.kappa
+
+
+def test_pcg_max_iter_iterate_matches_oracle(gpu, orc):
+    """Stopped after 7 iterations (ENOCONV), the returned x is the 7th iterate,
+    x update of the last step included, as in the oracle."""
+    W = w.workload("diffusion3d_16")
+    M = gpu.precondition(dev(W.A), block_size=64)
+    ref = orc.pcg(W.A, W.b, orc.Precond.uniform(W.A, 64), max_iter=7)
+    for check_every in (1, 2, 16):
+        x, info = gpu.pcg_solve(dev(W.A), M, W.b, max_iter=7, check_every=check_every)
+        assert info.status == ref.status == "ENOCONV" and info.iterations == ref.iterations == 7
+        xg = x.cpu().numpy()
+        assert np.linalg.norm(xg - ref.x) / np.linalg.norm(ref.x) <= 1e-12
+        assert abs(info.rel_res_true - ref.rel_res_true) <= 1e-12 * max(1.0, ref.rel_res_true)
+
+
+def test_pcg_poll_cadence_does_not_change_result(gpu):
+    """Polls only read the state: every poll cadence gives the same iterate
+    bits and iteration count."""
+    W = w.workload("diffusion3d_16")
+    A = dev(W.A)
+    M = gpu.precondition(A, block_size=64)
+    x0, i0 = gpu.pcg_solve(A, M, W.b, check_every=16)
+    for ce in (1, 3, 64):
+        x, info = gpu.pcg_solve(A, M, W.b, check_every=ce)
+        assert info.iterations == i0.iterations and info.status == "OK"
+        assert torch.equal(x, x0)
+
+
+def test_pcg_warm_start_matches_oracle(gpu, orc):
+    W = w.workload("diffusion3d_16")
+    x0 = np.random.default_rng(21).standard_normal(W.A.n)
+    M = gpu.precondition(dev(W.A), block_size=64)
+    x, info = gpu.pcg_solve(dev(W.A), M, W.b, x0=x0)
+    ref = orc.pcg(W.A, W.b, orc.Precond.uniform(W.A, 64), x0=x0)
+    assert info.status == ref.status == "OK"
+    assert abs(info.iterations - ref.iterations) <= max(1, int(np.ceil(0.03 * ref.iterations)))
+    assert np.linalg.norm(x.cpu().numpy() - ref.x) / np.linalg.norm(ref.x) <= 1e-10
+
+
+def test_pcg_streaming_long_and_empty_rows(gpu, orc):
+    """Row-block streaming with a row far longer than one LDS stage (a hub row
+    coupled to 3000 others) and rows with only a diagonal."""
+    n = 4000
+    rng = np.random.default_rng(22)
+    hub = 1234
+    others = np.setdiff1d(rng.choice(n, 3000, replace=False), [hub])
+    pi = np.concatenate([np.arange(n - 1), np.full(len(others), hub)])     # one entry per pair
+    pj = np.concatenate([np.arange(1, n), others])
+    keep = (pi < 3900) & (pj < 3900)                                        # rows >= 3900: diagonal only
+    pi, pj = pi[keep], pj[keep]
+    pv = -rng.random(len(pi))
+    rows, cols, vals = np.concatenate([pi, pj]), np.concatenate([pj, pi]), np.concatenate([pv, pv])
+    diag = np.bincount(rows, weights=np.abs(vals), minlength=n) + 0.5
+    A = w.from_coo(n, np.concatenate([rows, np.arange(n)]), np.concatenate([cols, np.arange(n)]),
+                   np.concatenate([vals, diag]))
+    assert np.diff(A.row_ptr).max() > 2048 and A.nnz / n < 12
+    b = w.rhs(n, 23)
+    for lanes in (-1, 0):
+        _pcg_parity(gpu, orc, A, b, 16, spmv_lanes=lanes)
