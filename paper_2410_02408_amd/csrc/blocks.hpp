@@ -147,6 +147,7 @@ __global__ __launch_bounds__(64) void k_setup(SetupArgs a) {
 #ifndef BJP_NT_TILES
 #define BJP_NT_TILES 1
 #endif
+
 // Tile loads: the packets are streamed once per application and exceed every
 // cache level, so they are loaded non-temporally (the vectors' lines stay
 // cached; measured at 128^3, n_b = 64 with the unpipelined loop: 130 us

@@ -296,7 +296,10 @@ __global__ __launch_bounds__(kWG) void k_spmv_stream(SpmvArgs a) {
 // that step's alpha), also when the decision ends the solve; then, unless the
 // solve is done, p_new = z + beta p_old.  The loads of the first kDirRows rows
 // of each thread are issued before the decision (which buffer is p_old
-// follows from src alone).
+// follows from src alone).  x is read and written non-temporally: nothing
+// reads it before the next direction update, and keeping it out of the caches
+// leaves them to p_new, which the product gathers next (measured at 128^3:
+// product 43 -> 38 us, this kernel 13.7 -> 15.4 us).
 #ifndef BJP_DIR_ROWS
 #define BJP_DIR_ROWS 8
 #endif
@@ -322,14 +325,14 @@ __global__ __launch_bounds__(kWG) void k_direction(const PcgState *src, PcgState
         const int i = min(i0 + j * stride, n - 1);
         zv[j] = z[i];
         pv[j] = pold[i];
-        xv[j] = xup ? x[i] : 0.0;
+        xv[j] = xup ? __builtin_nontemporal_load(x + i) : 0.0;
     }
     const PcgState L = shared_decide<OP>(src, dst, partials, nparts, hist);
     if (xup) {
 #pragma unroll
         for (int j = 0; j < kDirRows; ++j) {
             const int i = i0 + j * stride;
-            if (i < n) x[i] = __builtin_fma(alpha, pv[j], xv[j]);
+            if (i < n) __builtin_nontemporal_store(__builtin_fma(alpha, pv[j], xv[j]), x + i);
         }
         for (int i = i0 + kDirRows * stride; i < n; i += stride) x[i] = __builtin_fma(alpha, pold[i], x[i]);
     }
