@@ -161,10 +161,28 @@ class DeviceCsr:
                    torch.as_tensor(np.asarray(A.col_idx, np.int32), device=dev),
                    torch.as_tensor(np.asarray(A.val, np.float64), device=dev))
 
+    @classmethod
+    def from_torch(cls, t: torch.Tensor):
+        """From a square torch sparse CSR tensor on the GPU (indices converted
+        to int32 and values to float64; the tensor itself is not modified)."""
+        if t.layout != torch.sparse_csr or t.dim() != 2 or t.shape[0] != t.shape[1]:
+            raise TypeError("expected a square torch.sparse_csr tensor")
+        return cls(t.shape[0], t.crow_indices().to(torch.int32), t.col_indices().to(torch.int32),
+                   t.values().to(torch.float64))
+
     def struct(self) -> CsrT:
         return CsrT(self.n, self.nnz, self.row_ptr.data_ptr(),
                     self.col_idx.data_ptr() if self.nnz else 0,
                     self.val.data_ptr() if self.nnz else 0)
+
+
+def as_csr(A) -> DeviceCsr:
+    """A DeviceCsr as is, or a torch sparse CSR tensor converted to one."""
+    if isinstance(A, DeviceCsr):
+        return A
+    if isinstance(A, torch.Tensor) and A.layout == torch.sparse_csr:
+        return DeviceCsr.from_torch(A)
+    raise TypeError("expected a DeviceCsr or a torch.sparse_csr tensor")
 
 
 def _workspace(nbytes: int, device) -> torch.Tensor:
@@ -216,6 +234,7 @@ def precondition(A: DeviceCsr, block_size: int | None = None, offsets=None,
                  precision: str | int = "fp64") -> Precond:
     """bjp_precondition: extract, factor and invert the diagonal blocks."""
     L = load()
+    A = as_csr(A)
     prec = {"fp64": FP64, "fp32": FP32_STORE}.get(precision, precision)
     csr = A.struct()
     spec, keep = _spec(block_size, offsets)
@@ -259,6 +278,7 @@ class PcgWorkspace:
     """Reusable solver workspace for one matrix size."""
 
     def __init__(self, A: DeviceCsr):
+        A = as_csr(A)
         n = C.c_size_t()
         st = load().bjp_pcg_workspace(C.byref(A.struct()), C.byref(n))
         if st:
@@ -274,6 +294,7 @@ def pcg_solve(A: DeviceCsr, M: Precond | None, b, tol: float = 1e-10, max_iter: 
     """bjp_pcg_solve.  Returns (x, PcgInfo); solver failures are reported in
     info.status, argument/workspace/runtime errors raise BjpError."""
     L = load()
+    A = as_csr(A)
     dev = A.device
     b = _vec(b, dev)
     if out is not None:
@@ -323,6 +344,7 @@ def kappa_estimate(A: DeviceCsr, v0, steps: int, M: Precond | None = None,
                    workspace: KappaWorkspace | None = None) -> KappaInfo:
     """bjp_kappa_estimate: Lanczos estimate of kappa(M^-1 A) (kappa(A) if M is None)."""
     L = load()
+    A = as_csr(A)
     dev = A.device
     v0 = _vec(v0, dev)
     ws = workspace if workspace is not None and workspace.steps >= steps else KappaWorkspace(A, steps)
@@ -342,6 +364,7 @@ def kappa_estimate(A: DeviceCsr, v0, steps: int, M: Precond | None = None,
 def value_grad(A: DeviceCsr, lam: torch.Tensor, x: torch.Tensor, out: torch.Tensor | None = None):
     """bjp_value_grad: -lambda_i x_j on every stored entry of A (CSR order)."""
     L = load()
+    A = as_csr(A)
     g = torch.empty(A.nnz, dtype=torch.float64, device=A.device) if out is None else out
     st = L.bjp_value_grad(C.byref(A.struct()), _ptr(_vec(lam, A.device)), _ptr(_vec(x, A.device)),
                           _ptr(g), _stream(A.device))

@@ -390,3 +390,18 @@ def test_pcg_streaming_long_and_empty_rows(gpu, orc):
     b = w.rhs(n, 23)
     for lanes in (-1, 0):
         _pcg_parity(gpu, orc, A, b, 16, spmv_lanes=lanes)
+
+
+def test_torch_sparse_csr_input(gpu):
+    """A torch sparse CSR tensor is accepted wherever a DeviceCsr is."""
+    W = w.workload("poisson2d_32")
+    A = W.A
+    t = torch.sparse_csr_tensor(torch.as_tensor(A.row_ptr, dtype=torch.int64),
+                                torch.as_tensor(A.col_idx, dtype=torch.int64),
+                                torch.as_tensor(A.val), size=(A.n, A.n)).to(DEV)
+    Mt = gpu.precondition(t, block_size=16)
+    xt, it_ = gpu.pcg_solve(t, Mt, W.b)
+    Md = gpu.precondition(dev(A), block_size=16)
+    xd, id_ = gpu.pcg_solve(dev(A), Md, W.b)
+    assert it_.iterations == id_.iterations and torch.equal(xt, xd)
+    assert gpu.kappa_estimate(t, W.b, 20, M=Mt).kappa == gpu.kappa_estimate(dev(A), W.b, 20, M=Md).kappa
