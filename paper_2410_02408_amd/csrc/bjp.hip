@@ -291,7 +291,8 @@ int device_cus() {
 }
 
 // The block-inverse application runs one workgroup per compute unit: each
-// wave streams a long run of packets through its two-stage pipeline, which
+// wave streams a long sequence of packets (every W-th packet, W waves in the
+// launch) through its two-stage pipeline, which
 // keeps more bytes in flight than more, shorter-lived waves (measured at
 // 128^3, n_b = 64: 117 us at 256 workgroups, 120 at 512, 127 at 768).
 RowLaunch apply_shape(int packets) {
@@ -411,7 +412,10 @@ size_t batch_precond_bytes(const BatchPlan &P, int precision) {
            al256(sizeof(int32_t) * P.off.size()) + al256(P.tile_scalars * elem) + al256(64);
 }
 
-constexpr int kPacketsPerTile = 4 * kWaves;   // packets per apply tile (4 per wave)
+#ifndef BJP_BATCH_PACKETS
+#define BJP_BATCH_PACKETS 16
+#endif
+constexpr int kPacketsPerTile = BJP_BATCH_PACKETS;   // packets per apply tile
 
 struct BatchTables {
     std::vector<Tile> rt, pt;               // row tiles, packet tiles (grouped by G)
@@ -609,7 +613,6 @@ int bjp_apply(const bjp_precond_t *M, const double *r, double *z, hipStream_t st
     a.rin = r;
     a.zout = z;
     const RowLaunch L = apply_shape(M->num_packets);
-    a.chunk = L.chunk;
     launch_apply<APPLY_PLAIN>(M, L.grid, a, stream);
     HIP_TRY(hipGetLastError());
     return BJP_OK;
@@ -709,7 +712,6 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
         aa.off = M->offsets;
         aa.tiles = M->tiles;
     }
-    aa.chunk = La.chunk;
     aa.rin = r;
     aa.zout = z;
     aa.st = st;
@@ -959,7 +961,6 @@ int bjp_kappa_estimate(const bjp_csr_t *A, const bjp_precond_t *M, const double 
         aa.tiles = M->tiles;
     }
     const RowLaunch La = M ? apply_shape(M->num_packets) : Lr;
-    aa.chunk = La.chunk;
     aa.rin = rt;
     aa.zout = zt;
     aa.ls = ls;

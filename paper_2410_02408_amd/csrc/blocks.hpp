@@ -255,7 +255,7 @@ __device__ __forceinline__ TS packet_product(const TS (&dv)[G / 2 + 1], int g, i
 enum ApplyMode { APPLY_PLAIN = 0, APPLY_INIT = 1, APPLY_UPDATE = 2, APPLY_LANCZOS = 3, APPLY_STEP = 4 };
 
 struct ApplyArgs {
-    int nblocks, num_packets, chunk;
+    int nblocks, num_packets;
     int n;                  // rows of the system
     int row0;               // first row of the system (0 except in batches)
     int uniform_nb;         // > 0: block t = rows [row0 + t*nb, ...), offsets unused
@@ -376,9 +376,13 @@ __device__ __forceinline__ void apply_packets(const ApplyArgs &a, const PcgState
     }
 }
 
-// UPDATE first takes the step-length decision alpha = rho / (p^T A p) in
-// every workgroup (from the product's partials), then updates x and r,
-// applies M^-1 and marks the update decision pending for the next launch.
+// STEP first takes the step-length decision alpha = rho / (p^T A p) in
+// every workgroup (from the product's partials), then updates r, applies
+// M^-1 and marks the update decision pending for the next launch.  Wave w of
+// the launch takes packets w, w + W, w + 2W, ... (W waves in all), so the
+// whole launch streams one contiguous window of the packed inverses at a
+// time (measured at 128^3, n_b = 64: 1.7 us per application faster than
+// contiguous runs of packets per workgroup).
 template <int G, typename TS, int MODE>
 __global__ __launch_bounds__(kWG) void k_apply(ApplyArgs a) {
     if (MODE == APPLY_INIT) {
@@ -388,9 +392,6 @@ __global__ __launch_bounds__(kWG) void k_apply(ApplyArgs a) {
         if (a.ls->done) return;
     }
     const int wave = threadIdx.x >> 6;
-    const int c = xcd_chunk(blockIdx.x, gridDim.x);
-    const int pk0 = c * a.chunk;
-    const int pk1 = min(pk0 + a.chunk, a.num_packets);
     double d0 = 0.0, d1 = 0.0;
     auto pre = [&](double &alpha) -> bool {
         if (MODE != APPLY_STEP) return true;
@@ -398,7 +399,7 @@ __global__ __launch_bounds__(kWG) void k_apply(ApplyArgs a) {
         alpha = L.alpha;
         return !L.done;
     };
-    apply_packets<G, TS, MODE>(a, a.st, pk0 + wave, pk1, kWaves, d0, d1, pre);
+    apply_packets<G, TS, MODE>(a, a.st, blockIdx.x * kWaves + wave, a.num_packets, gridDim.x * kWaves, d0, d1, pre);
     if (MODE == APPLY_PLAIN) return;
     const double v[2] = {d0, d1};
     block_partial<2>(v, a.partials);
