@@ -124,10 +124,13 @@ int bjp_precondition(const bjp_csr_t *A, const bjp_block_spec_t *spec, int preci
  * overlap.  Asynchronous. */
 int bjp_apply(const bjp_precond_t *M, const double *r, double *z, hipStream_t stream);
 
-/* Optional kernel timing.  When a solver is given one, every launch of the
- * selected kernel inside its iteration loop is bracketed by a pair of
- * events recorded on the solver's stream: events[2i] before, events[2i+1]
- * after launch i, for the first `capacity` launches.  The events are
+/* Optional kernel timing.  When a solver is given one, every stride-th
+ * launch of the selected kernel inside its iteration loop (launches 0,
+ * stride, 2*stride, ...) is bracketed by a pair of events recorded on the
+ * solver's stream: events[2i] before, events[2i+1] after the i-th timed
+ * launch, for the first `capacity` timed launches.  Each event pair adds a
+ * few microseconds between the launches it brackets, so a stride above 1
+ * keeps the timing from slowing the solve it measures.  The events are
  * created and destroyed by the caller (host array of 2*capacity handles). */
 typedef enum {
     BJP_KERNEL_APPLY = 0,   /* the block-inverse application (x, r update + z = M^-1 r) */
@@ -138,7 +141,7 @@ typedef struct {
     int32_t kernel;         /* bjp_kernel_id */
     int32_t capacity;       /* event pairs available */
     int32_t recorded;       /* out: pairs recorded */
-    int32_t pad;
+    int32_t stride;         /* time every stride-th launch (0 or 1: every launch) */
     hipEvent_t *events;     /* host array [2*capacity] */
 } bjp_timing_t;
 

@@ -43,7 +43,7 @@ class PrecondT(C.Structure):
 
 class TimingT(C.Structure):
     _fields_ = [("kernel", C.c_int32), ("capacity", C.c_int32), ("recorded", C.c_int32),
-                ("pad", C.c_int32), ("events", C.c_void_p)]
+                ("stride", C.c_int32), ("events", C.c_void_p)]
 
 
 class PcgOptsT(C.Structure):
@@ -60,15 +60,17 @@ class KernelTimer:
     """Event pairs that the solver records around one kernel class.
 
     Uses torch.cuda.Event objects (HIP events); durations are read after the
-    solve with Event.elapsed_time."""
+    solve with Event.elapsed_time.  With stride k only every k-th launch is
+    timed (each event pair delays the launches it brackets by a few
+    microseconds)."""
 
-    def __init__(self, kernel: int, capacity: int):
+    def __init__(self, kernel: int, capacity: int, stride: int = 1):
         self.events = [torch.cuda.Event(enable_timing=True) for _ in range(2 * capacity)]
         for e in self.events:
             e.record()          # materialise the underlying HIP event
         torch.cuda.synchronize()
         self._handles = (C.c_void_p * (2 * capacity))(*[e.cuda_event for e in self.events])
-        self.struct = TimingT(kernel, capacity, 0, 0, C.cast(self._handles, C.c_void_p))
+        self.struct = TimingT(kernel, capacity, 0, max(int(stride), 1), C.cast(self._handles, C.c_void_p))
 
     def durations_ms(self) -> list:
         torch.cuda.synchronize()

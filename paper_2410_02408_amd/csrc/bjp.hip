@@ -740,10 +740,16 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
     };
     bjp_timing_t *tm = o.timing;
     if (tm) tm->recorded = 0;
+    const int tm_stride = tm && tm->stride > 1 ? tm->stride : 1;
+    long long tm_seen = 0;      // launches of the timed kernel so far
     auto mark = [&](int kernel, int which) {
-        if (!tm || tm->kernel != kernel || tm->recorded >= tm->capacity || !tm->events) return;
-        (void)hipEventRecord(tm->events[2 * tm->recorded + which], stream);
-        if (which == 1) tm->recorded++;
+        if (!tm || tm->kernel != kernel || !tm->events) return;
+        const bool timed = tm_seen % tm_stride == 0 && tm->recorded < tm->capacity;
+        if (timed) (void)hipEventRecord(tm->events[2 * tm->recorded + which], stream);
+        if (which == 1) {
+            if (timed) tm->recorded++;
+            ++tm_seen;
+        }
     };
     // One iteration is three launches, each taking the scalar decision of the
     // previous one as its prologue (no separate finish launches):
