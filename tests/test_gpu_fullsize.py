@@ -115,3 +115,51 @@ def test_fullsize_adjoint_identity(gpu, orc):
     # factored product: compare up to that rounding)
     ref = orc.edge_grad(g, lam, xg)
     np.testing.assert_allclose(ct.grad.cpu().numpy(), ref, rtol=1e-7, atol=1e-10 * np.abs(ref).max())
+
+
+
+@pytest.fixture(scope="module")
+def powerlaw():
+    """Power-law workload (N = 4,194,304, 134M nonzeros, n_b = 32) and the
+    GPU's solves of it, shared by the two tests below (generating it takes
+    the better part of the time)."""
+    A_h = w.powerlaw_spd(1 << 22, seed=4)
+    return A_h, w.rhs(A_h.n, 4), {}
+
+
+def _powerlaw_solves(gpu, powerlaw):
+    A_h, b_h, solves = powerlaw
+    if not solves:
+        A = gpu.DeviceCsr.from_host(A_h, DEV)
+        b = torch.as_tensor(b_h, device=DEV)
+        for prec in ("fp64", "fp32"):
+            M = gpu.precondition(A, block_size=32, precision=prec)
+            x, info = gpu.pcg_solve(A, M, b, tol=1e-10)
+            solves[prec] = (x.cpu().numpy(), info)
+    return solves
+
+
+def test_fullsize_precision_paths(gpu, powerlaw):
+    """Both the FP64 path and the FP32-stored inverses reach the 1e-10 true
+    residual; the two solutions agree far below it."""
+    s = _powerlaw_solves(gpu, powerlaw)
+    for prec, (x, info) in s.items():
+        assert info.status == "OK" and info.rel_res_true <= 1e-10, prec
+        assert np.all(np.isfinite(x))
+    x64, x32 = s["fp64"][0], s["fp32"][0]
+    assert np.linalg.norm(x32 - x64) / np.linalg.norm(x64) <= 1e-10
+
+
+def test_fullsize_precision_vs_oracle(gpu, orc, powerlaw):
+    """Both solutions agree with the oracle's FP64 solve to 1e-10 relative,
+    in the same number of iterations (within one)."""
+    A_h, b_h, _ = powerlaw
+    s = _powerlaw_solves(gpu, powerlaw)
+    ref = orc.pcg(A_h, b_h, orc.Precond.uniform(A_h, 32), tol=1e-10)
+    assert ref.status == "OK"
+    for prec, (x, info) in s.items():
+        err = np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x)
+        print(f"{prec}: {info.iterations} iterations (oracle {ref.iterations}), "
+              f"relative error against the oracle {err:.2e}", flush=True)
+        assert abs(info.iterations - ref.iterations) <= 1, (prec, info.iterations, ref.iterations)
+        assert err <= 1e-10, (prec, err)
