@@ -220,7 +220,7 @@ void launch_setup(int G, int grid, const SetupArgs &a, hipStream_t s) {
         case 8: hipLaunchKernelGGL((k_setup<8, TS>), dim3(grid), dim3(64), 0, s, a); break;
         case 16: hipLaunchKernelGGL((k_setup<16, TS>), dim3(grid), dim3(64), 0, s, a); break;
         case 32: hipLaunchKernelGGL((k_setup<32, TS>), dim3(grid), dim3(64), 0, s, a); break;
-        default: hipLaunchKernelGGL((k_setup<64, TS>), dim3(grid), dim3(64), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_setup64<TS>), dim3(grid), dim3(64), 0, s, a); break;
     }
 }
 
