@@ -405,3 +405,21 @@ def test_torch_sparse_csr_input(gpu):
     xd, id_ = gpu.pcg_solve(dev(A), Md, W.b)
     assert it_.iterations == id_.iterations and torch.equal(xt, xd)
     assert gpu.kappa_estimate(t, W.b, 20, M=Mt).kappa == gpu.kappa_estimate(dev(A), W.b, 20, M=Md).kappa
+
+
+@pytest.mark.parametrize("stride", [1, 4])
+def test_kernel_timer_stride(gpu, stride):
+    """Every stride-th application is timed; timing leaves the result bitwise
+    unchanged."""
+    W = w.workload("diffusion3d_20")
+    A = dev(W.A)
+    M = gpu.precondition(A, block_size=64)
+    x0, info0 = gpu.pcg_solve(A, M, W.b, tol=W.tol)
+    tm = gpu.KernelTimer(gpu.KERNEL_APPLY, 512, stride=stride)
+    x1, info1 = gpu.pcg_solve(A, M, W.b, tol=W.tol, timer=tm)
+    assert info1.iterations == info0.iterations and torch.equal(x0, x1)
+    n = tm.struct.recorded
+    # launches past convergence may be timed too (polls overlap the iterations)
+    assert -(-info1.iterations // stride) <= n <= 512
+    d = tm.durations_ms()
+    assert len(d) == n and all(v > 0 for v in d)
