@@ -61,7 +61,8 @@ __global__ __launch_bounds__(kWG) void k_spmv_tiles(SpmvArgs a, TileSpan ts) {
     block_partial_at<2>(v, a.partials, ts.stride, t < ts.end ? t : -1);
 }
 
-// Row-block streaming schedule over row tiles (short rows).
+// Row-block streaming schedule over row tiles (short rows); CSR loads are
+// non-temporal (the batch's matrix exceeds the last-level cache).
 template <int MODE>
 __global__ __launch_bounds__(kWG) void k_spmv_tiles_stream(SpmvArgs a, TileSpan ts) {
     const int t = tile_of(ts);
@@ -70,7 +71,7 @@ __global__ __launch_bounds__(kWG) void k_spmv_tiles_stream(SpmvArgs a, TileSpan 
         const Tile tl = ts.tiles[t];
         const PcgState *st = a.st + tl.s;
         const bool run = (MODE == SPMV_RESID && a.resid_phase == 1) || !st->done;
-        if (run) spmv_stream_rows<MODE>(a, st->it, tl.a0, tl.a1, d0, d1);
+        if (run) spmv_stream_rows<MODE, true>(a, st->it, tl.a0, tl.a1, d0, d1);
     }
     const double v[2] = {d0, d1};
     block_partial_at<2>(v, a.partials, ts.stride, t < ts.end ? t : -1);

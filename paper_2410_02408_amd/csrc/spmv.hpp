@@ -56,18 +56,17 @@ struct SpmvArgs {
     double *partials;       // per-workgroup dots (see the modes)
 };
 
-#ifndef BJP_NT_CSR
-#define BJP_NT_CSR 0
-#endif
-// CSR values and column indices are streamed once per product; loading them
-// non-temporally keeps the gathered vector resident in the caches.
-template <typename T>
+// CSR values and column indices are streamed once per product.  Loaded
+// non-temporally (NT) they leave the caches to the gathered vector; that pays
+// only when the matrix exceeds the last-level cache: a single system's CSR
+// that fits stays resident from one product to the next if loaded normally
+// (measured at 128^3: +7 us per product with NT loads), while the batch's
+// 3.1 GB CSR does not (row-block streaming over the 512-system batch: 58.2 ->
+// 55.3 ms per solve with NT loads).
+template <bool NT = false, typename T>
 __device__ __forceinline__ T csr_load(const T *p) {
-#if BJP_NT_CSR
-    return __builtin_nontemporal_load(p);
-#else
-    return *p;
-#endif
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
 }
 
 // The updated direction p_new = z + beta p_old of row i (one rounding).
@@ -213,7 +212,7 @@ constexpr int kStreamRows = kWG;
 constexpr int kStreamCap = BJP_STREAM_CAP;
 constexpr int kStreamPer = kStreamCap / kWG;
 
-template <int MODE>
+template <int MODE, bool NT = false>
 __device__ __forceinline__ void spmv_stream_rows(const SpmvArgs &a, int it, int r0, int r1, double &d0,
                                                  double &d1) {
     __shared__ double prod[kStreamCap];
@@ -238,8 +237,8 @@ __device__ __forceinline__ void spmv_stream_rows(const SpmvArgs &a, int it, int 
             for (int j = 0; j < kStreamPer; ++j) {
                 const int k = c0 + j * kWG + tid;
                 const int kc = k < c1 ? k : c0;
-                col[j] = csr_load(ci + kc);
-                vv[j] = csr_load(val + kc);
+                col[j] = csr_load<NT>(ci + kc);
+                vv[j] = csr_load<NT>(val + kc);
             }
 #pragma unroll
             for (int j = 0; j < kStreamPer; ++j) prod[j * kWG + tid] = vv[j] * m.gather(col[j]);
