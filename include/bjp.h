@@ -59,7 +59,11 @@ typedef enum {
 
 /* Sparse matrix in CSR form (device arrays).  Full symmetric storage (both
  * triangles), int32 indices, FP64 values; duplicate (i, j) entries are
- * summed, columns inside a row may be unsorted.  n >= 0; nnz = row_ptr[n]. */
+ * summed, columns inside a row may be unsorted.  n >= 0; nnz = row_ptr[n].
+ * n and nnz are at most BJP_MAX_DIM (a margin below INT32_MAX keeps every
+ * index the kernels form, such as one grid stride past the last row, inside
+ * int32); larger sizes are rejected with BJP_EINVAL. */
+#define BJP_MAX_DIM (2147483647 - (1 << 24))
 typedef struct {
     int32_t n;
     int32_t nnz;

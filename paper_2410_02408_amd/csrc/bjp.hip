@@ -52,7 +52,7 @@ struct Carver {
 };
 
 int check_csr_host(const bjp_csr_t *A) {
-    if (!A || A->n < 0 || A->nnz < 0) return BJP_EINVAL;
+    if (!A || A->n < 0 || A->nnz < 0 || A->n > BJP_MAX_DIM || A->nnz > BJP_MAX_DIM) return BJP_EINVAL;
     if (A->n > 0 && !A->row_ptr) return BJP_EINVAL;
     if (A->nnz > 0 && (!A->col_idx || !A->val)) return BJP_EINVAL;
     return BJP_OK;

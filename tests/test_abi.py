@@ -80,3 +80,26 @@ def test_argument_errors_without_gpu(lib):
     assert L.bjp_pcg_solve(C.byref(csr), None, 1, 1, None, None, 0, C.byref(info), None) == -6
     kinfo = bjp.KappaInfoT()
     assert L.bjp_kappa_estimate(C.byref(csr), None, 1, 0, None, None, None, 0, C.byref(kinfo), None) == -1
+
+
+def test_maximum_sizes_without_gpu(lib):
+    """n and nnz up to BJP_MAX_DIM are accepted (size queries succeed, with
+    64-bit byte counts), one more is rejected: every index the kernels form
+    stays inside int32."""
+    from paper_2410_02408_amd import bjp
+
+    text = open(HEADER).read()
+    m = re.search(r"#define BJP_MAX_DIM \(2147483647 - \(1 << (\d+)\)\)", text)
+    assert m
+    max_dim = 2147483647 - (1 << int(m.group(1)))
+    L = bjp.load()
+    n = C.c_size_t()
+    ok = bjp.CsrT(max_dim, max_dim, 1, 1, 1)
+    assert L.bjp_pcg_workspace(C.byref(ok), C.byref(n)) == 0
+    assert n.value >= 5 * 8 * max_dim
+    spec = bjp.BlockSpecT(64, 0, None)
+    assert L.bjp_precondition_workspace(C.byref(ok), C.byref(spec), 0, C.byref(n)) == 0
+    assert n.value >= (max_dim // 64) * 2080 * 8
+    for big in [bjp.CsrT(max_dim + 1, 10, 1, 1, 1), bjp.CsrT(10, max_dim + 1, 1, 1, 1)]:
+        assert L.bjp_pcg_workspace(C.byref(big), C.byref(n)) == -1
+        assert L.bjp_precondition_workspace(C.byref(big), C.byref(spec), 0, C.byref(n)) == -1
