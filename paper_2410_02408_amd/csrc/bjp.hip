@@ -290,13 +290,25 @@ int device_cus() {
     return cus[dev];
 }
 
-// The block-inverse application runs one workgroup per compute unit: each
-// wave streams a long sequence of packets (every W-th packet, W waves in the
-// launch) through its two-stage pipeline, which
-// keeps more bytes in flight than more, shorter-lived waves (measured at
-// 128^3, n_b = 64: 117 us at 256 workgroups, 120 at 512, 127 at 768).
-RowLaunch apply_shape(int packets) {
-    const int grid = round8(std::min(ceil_div(packets, kWaves), std::min(device_cus(), kMaxRedWG)));
+// The block-inverse application runs one workgroup per compute unit for
+// 64-row groups: each wave streams a long sequence of packets (every W-th
+// packet, W waves in the launch) through its two-stage pipeline, which keeps
+// more bytes in flight than more, shorter-lived waves (measured at 128^3,
+// n_b = 64: 117 us at 256 workgroups, 120 at 512, 127 at 768; FP32 tiles:
+// 49.7 us at one workgroup per CU, 51.0 at two).  Narrower groups have
+// smaller packets, and one workgroup per CU then holds too few bytes in
+// flight to cover the memory latency: those launches take enough workgroups
+// per CU to keep about 16 KB of packets (tiles and vectors) in their
+// pipelines per CU (measured at 128^3: n_b = 8 24.0 -> 18.9 us, n_b = 32 FP32
+// 38.7 -> 30.7 us; 32 KB per CU was slower for every block size).
+constexpr int kApplyInflight = 16384;
+
+RowLaunch apply_shape(const bjp_precond_t *M) {
+    const int packets = M->num_packets;
+    const int elem = M->precision == BJP_FP32_STORE ? 4 : 8;
+    const int bytes = M->packet_elems * elem + 64 * 32;   // tiles + q, r read, r, z written
+    const int per_cu = M->group == 64 ? 1 : std::max(1, std::min(8, (kApplyInflight + bytes - 1) / bytes));
+    const int grid = round8(std::min(ceil_div(packets, kWaves), std::min(device_cus() * per_cu, kMaxRedWG)));
     return {grid, ceil_div(packets, grid)};
 }
 
@@ -612,7 +624,7 @@ int bjp_apply(const bjp_precond_t *M, const double *r, double *z, hipStream_t st
     a.tiles = M->tiles;
     a.rin = r;
     a.zout = z;
-    const RowLaunch L = apply_shape(M->num_packets);
+    const RowLaunch L = apply_shape(M);
     launch_apply<APPLY_PLAIN>(M, L.grid, a, stream);
     HIP_TRY(hipGetLastError());
     return BJP_OK;
@@ -674,7 +686,7 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
 
     const int gs = spmv_schedule(o.spmv_lanes, A);
     const RowLaunch Ls = spmv_shape(n, gs);
-    const RowLaunch La = M ? apply_shape(M->num_packets) : rows_shape(n);
+    const RowLaunch La = M ? apply_shape(M) : rows_shape(n);
     const int fill_grid = std::min(ceil_div(n, kWG), 4096);
 
     hipLaunchKernelGGL(k_pcg_state_init, dim3(1), dim3(64), 0, stream, st, o.tol, o.max_iter);
@@ -966,7 +978,7 @@ int bjp_kappa_estimate(const bjp_csr_t *A, const bjp_precond_t *M, const double 
         aa.off = M->offsets;
         aa.tiles = M->tiles;
     }
-    const RowLaunch La = M ? apply_shape(M->num_packets) : Lr;
+    const RowLaunch La = M ? apply_shape(M) : Lr;
     aa.rin = rt;
     aa.zout = zt;
     aa.ls = ls;
