@@ -65,6 +65,12 @@ __global__ void k_fill(double *p, int n, double v) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
 }
 
+// off[t] = t * nb for t < nblocks, off[nblocks] = n.
+__global__ void k_uniform_offsets(int32_t *off, int nblocks, int nb, int n) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t <= nblocks; t += gridDim.x * blockDim.x)
+        off[t] = t == nblocks ? n : (int32_t)((long long)t * nb);
+}
+
 __global__ void k_flags_init(int32_t *flags) {
     if (threadIdx.x == 0) {
         flags[0] = INT_MAX;
@@ -154,18 +160,26 @@ void finish(const FinishArgs &f, int nparts, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // partition
 // ---------------------------------------------------------------------------
+// Uniform partitions keep no host copy of their offsets (the device forms
+// them); explicit ones are copied from the caller.
 struct Partition {
-    std::vector<int32_t> off;
+    std::vector<int32_t> off;   // explicit partitions: nblocks + 1 offsets
+    int uniform = 0;            // > 0: blocks of `uniform` rows, last one ragged
     int nblocks = 0, G = 1, packets = 0, E = 64;
 };
 
 int make_partition(int n, const bjp_block_spec_t *spec, Partition &P) {
     if (!spec) return BJP_EINVAL;
     P.off.clear();
+    P.uniform = 0;
     if (spec->block_size > 0) {
         if (spec->block_size > BJP_MAX_BLOCK) return BJP_EINVAL;
-        for (long long s = 0; s < n; s += spec->block_size) P.off.push_back((int32_t)s);
-        P.off.push_back(n);
+        P.uniform = spec->block_size;
+        P.nblocks = ceil_div(n, spec->block_size);
+        P.G = pow2_at_least(n > 0 ? std::min(spec->block_size, n) : 1);
+        P.packets = ceil_div(P.nblocks, 64 / P.G);
+        P.E = packet_elems(P.G);
+        return BJP_OK;
     } else if (spec->block_size == 0) {
         if (spec->num_blocks < 0 || !spec->offsets) return BJP_EINVAL;
         P.off.assign(spec->offsets, spec->offsets + spec->num_blocks + 1);
@@ -188,7 +202,7 @@ int make_partition(int n, const bjp_block_spec_t *spec, Partition &P) {
 
 size_t precond_ws_bytes(const Partition &P, int precision) {
     const size_t s = precision == BJP_FP32_STORE ? 4 : 8;
-    return al256(sizeof(int32_t) * P.off.size()) + al256((size_t)P.packets * P.E * s) + al256(64);
+    return al256(sizeof(int32_t) * ((size_t)P.nblocks + 1)) + al256((size_t)P.packets * P.E * s) + al256(64);
 }
 
 int run_validate(const bjp_csr_t *A, int32_t *flags, hipStream_t stream) {
@@ -576,7 +590,7 @@ int bjp_precondition(const bjp_csr_t *A, const bjp_block_spec_t *spec, int preci
     if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255)) return BJP_EWORKSPACE;
 
     Carver cv{static_cast<char *>(ws)};
-    int32_t *off = cv.take<int32_t>(P.off.size());
+    int32_t *off = cv.take<int32_t>((size_t)P.nblocks + 1);
     void *tiles = cv.base + cv.used;
     cv.used += al256((size_t)P.packets * P.E * (precision == BJP_FP32_STORE ? 4 : 8));
     int32_t *flags = cv.take<int32_t>(16);
@@ -593,10 +607,16 @@ int bjp_precondition(const bjp_csr_t *A, const bjp_block_spec_t *spec, int preci
 
     st = run_validate(A, flags, stream);
     if (st != BJP_OK) return st;
-    if (A->n == 0) return BJP_OK;
-
-    HIP_TRY(hipMemcpyAsync(off, P.off.data(), sizeof(int32_t) * P.off.size(), hipMemcpyHostToDevice,
-                           stream));
+    if (P.uniform > 0)
+        hipLaunchKernelGGL(k_uniform_offsets, dim3(std::min(ceil_div(P.nblocks + 1, kWG), 4096)), dim3(kWG), 0,
+                           stream, off, P.nblocks, P.uniform, A->n);
+    else
+        HIP_TRY(hipMemcpyAsync(off, P.off.data(), sizeof(int32_t) * P.off.size(), hipMemcpyHostToDevice,
+                               stream));
+    if (A->n == 0) {
+        HIP_TRY(hipStreamSynchronize(stream));
+        return BJP_OK;
+    }
     SetupArgs sa{A->row_ptr, A->col_idx, A->val, off, P.nblocks, tiles, flags, 0};
     if (precision == BJP_FP32_STORE) launch_setup<float>(P.G, P.packets, sa, stream);
     else launch_setup<double>(P.G, P.packets, sa, stream);
