@@ -231,10 +231,10 @@ void launch_setup(int G, int grid, const SetupArgs &a, hipStream_t s) {
         case 1: hipLaunchKernelGGL((k_setup<1, TS>), dim3(grid), dim3(64), 0, s, a); break;
         case 2: hipLaunchKernelGGL((k_setup<2, TS>), dim3(grid), dim3(64), 0, s, a); break;
         case 4: hipLaunchKernelGGL((k_setup<4, TS>), dim3(grid), dim3(64), 0, s, a); break;
-        case 8: hipLaunchKernelGGL((k_setup<8, TS>), dim3(grid), dim3(64), 0, s, a); break;
-        case 16: hipLaunchKernelGGL((k_setup<16, TS>), dim3(grid), dim3(64), 0, s, a); break;
-        case 32: hipLaunchKernelGGL((k_setup<32, TS>), dim3(grid), dim3(64), 0, s, a); break;
-        default: hipLaunchKernelGGL((k_setup64<TS>), dim3(grid), dim3(64), 0, s, a); break;
+        case 8: hipLaunchKernelGGL((k_setup_reg<8, TS>), dim3(grid), dim3(64), 0, s, a); break;
+        case 16: hipLaunchKernelGGL((k_setup_reg<16, TS>), dim3(grid), dim3(64), 0, s, a); break;
+        case 32: hipLaunchKernelGGL((k_setup_reg<32, TS>), dim3(grid), dim3(64), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_setup_reg<64, TS>), dim3(grid), dim3(64), 0, s, a); break;
     }
 }
 

@@ -154,101 +154,104 @@ __device__ __forceinline__ double lane_value(double v, int l) {
     return __hiloint2double(hi, lo);
 }
 
-// Build for blocks of up to 64 rows in 64-lane groups (G = 64, one block per
-// wave): the same arithmetic as k_setup<64> in the same order (the stored
-// inverses agree bit for bit up to the sign of exact zeros), with the rows
-// held in registers instead of LDS; measured at 128^3, n_b = 64: 1.7 ms
-// instead of 9.3 ms for the 32,768 blocks.  Lane i keeps row i of the block while it
-// is factorised, then lane c forms column c of L^-1 and multiplies it with
-// the other columns.  What a step needs from other lanes (a column of L, a
-// row of L, the columns of L^-1) is written to LDS once and read back by all
-// lanes at the same address (a broadcast) into registers, all of a step's
-// reads issued before its arithmetic; the loops over columns are unrolled so
-// every register index is a compile-time constant.  Rows past the block's
-// end are set to the identity, which leaves the block's own entries
-// unchanged (its couplings to them are zero) and keeps bounds tests out of
-// the unrolled loops.
-template <typename TS>
-__global__ __launch_bounds__(64) void k_setup64(SetupArgs a) {
-    constexpr int G = 64, LDM = 66, E = packet_elems(G);   // LDM: 16-byte aligned rows
-    __shared__ __align__(16) double Mx[G][LDM];
-    __shared__ __align__(16) double cb[2][G];
-    __shared__ double Wd[G];
-    const int lane = threadIdx.x;
-    const int t = blockIdx.x;
+// Build with the rows held in registers (groups of G = 8 .. 64 lanes, P =
+// 64/G blocks per wave): the same arithmetic as k_setup<G> in the same order
+// (the stored inverses agree bit for bit up to the sign of exact zeros).
+// Lane i of group g keeps row i of block g while it is factorised, then
+// forms column i of L^-1 and multiplies it with the other columns.  What a
+// step needs from other lanes (a pivot, a column of L, a row of L, the
+// columns of L^-1) is read from a lane of the group (readlane for one group
+// per wave, a permute otherwise) or written to LDS once and read back by the
+// group at one address (a broadcast), all of a step's reads issued before
+// its arithmetic; the loops over columns are unrolled so every register
+// index is a compile-time constant.  Rows past a block's end are set to the
+// identity, which leaves the block's own entries unchanged (its couplings to
+// them are zero) and keeps bounds tests out of the unrolled loops.  Measured
+// at 128^3, n_b = 64: 1.7 ms instead of 9.3 ms for the 32,768 blocks.
+template <int G, typename TS>
+__global__ __launch_bounds__(64) void k_setup_reg(SetupArgs a) {
+    static_assert(G >= 8 && G <= 64 && (G & (G - 1)) == 0, "paired diagonals need G / 2 even");
+    constexpr int P = 64 / G, LDM = G + 2, E = packet_elems(G);   // LDM: 16-byte aligned rows
+    __shared__ __align__(16) double Mx[64][LDM];
+    __shared__ __align__(16) double cb[2][64];
+    __shared__ double Wd[64];
+    const int lane = threadIdx.x, g = lane / G, i = lane % G, base = g * G;
+    const int t = blockIdx.x * P + g;
     int s = 0, n = 0;
     if (t < a.nblocks) {
         s = a.off[t];
         n = a.off[t + 1] - s;
     }
 
-    // 1. extract row s + lane of the diagonal block (duplicates summed)
+    // 1. extract row s + i of the diagonal block (duplicates summed)
 #pragma unroll
     for (int c = 0; c < G; ++c) Mx[lane][c] = 0.0;
-    if (lane < n) {
-        const int row = s + lane;
+    if (i < n) {
+        const int row = s + i;
         const int kb = a.rp[row], ke = a.rp[row + 1];
         for (int k = kb; k < ke; ++k) {
             const int c = a.ci[k] - s;
             if (c >= 0 && c < n) Mx[lane][c] += a.val[k];
         }
     } else {
-        Mx[lane][lane] = 1.0;
+        Mx[lane][i] = 1.0;
     }
     double r[G];
 #pragma unroll
     for (int c = 0; c < G; ++c) r[c] = Mx[lane][c];
 
-    // 2. right-looking Cholesky: step j takes the pivot from lane j, scales
-    //    column j below it and updates the trailing rows (lanes > j) with
-    //    column j broadcast through LDS
+    // 2. right-looking Cholesky: step j takes the pivot from row j, scales
+    //    column j below it and updates the trailing rows (i > j) with column
+    //    j broadcast through LDS
     bool bad = false;
 #pragma unroll
     for (int j = 0; j < G; ++j) {
-        const double d = lane_value(r[j], j);
+        double d;
+        if constexpr (G == 64) d = lane_value(r[j], j);
+        else d = __shfl(r[j], base + j, 64);
         if (j < n && !(d > 0.0 && isfinite(d))) bad = true;
         const double ljj = sqrt(d);
-        if (lane > j) r[j] = r[j] / ljj;
-        if (lane == j) r[j] = ljj;
+        if (i > j) r[j] = r[j] / ljj;
+        if (i == j) r[j] = ljj;
         if (j + 1 < G) {
-            double *col = cb[j & 1];
-            col[lane] = r[j];
+            double *col = cb[j & 1] + base;
+            col[i] = r[j];
             __syncthreads();
             double cv[G];
 #pragma unroll
             for (int k = j + 1; k < G; ++k) cv[k] = col[k];
             __builtin_amdgcn_sched_barrier(0);
-            if (lane > j) {
+            if (i > j) {
 #pragma unroll
                 for (int k = j + 1; k < G; ++k) r[k] -= r[j] * cv[k];
             }
         }
     }
-    if (bad && lane == 0) atomicMin(&a.flags[0], a.block_base + t);
+    if (bad && i == 0) atomicMin(&a.flags[0], a.block_base + t);
 
-    // 3. W = L^-1 by columns: lane c forms W[ii][c] row by row from row ii
-    //    of L (broadcast); W[c][c] = 1 / L[c][c], zeros above
+    // 3. W = L^-1 by columns: lane i forms W[ii][i] row by row from row ii
+    //    of L (broadcast); W[i][i] = 1 / L[i][i], zeros above
 #pragma unroll
     for (int c = 0; c < G; ++c) Mx[lane][c] = r[c];
-    Wd[lane] = 1.0 / Mx[lane][lane];
+    Wd[lane] = 1.0 / Mx[lane][i];
     __syncthreads();
     double w[G];
     {
         const double wself = Wd[lane];
 #pragma unroll
-        for (int k = 0; k < G; ++k) w[k] = (k == lane) ? wself : 0.0;
+        for (int k = 0; k < G; ++k) w[k] = (k == i) ? wself : 0.0;
     }
 #pragma unroll
     for (int ii = 1; ii < G; ++ii) {
         double lv[G];
 #pragma unroll
-        for (int k = 0; k < ii; ++k) lv[k] = Mx[ii][k];
-        const double wd = Wd[ii];
+        for (int k = 0; k < ii; ++k) lv[k] = Mx[base + ii][k];
+        const double wd = Wd[base + ii];
         __builtin_amdgcn_sched_barrier(0);
         double acc = 0.0;
 #pragma unroll
         for (int k = 0; k < ii; ++k) acc += lv[k] * w[k];
-        if (lane < ii) w[ii] = -acc * wd;
+        if (i < ii) w[ii] = -acc * wd;
     }
     __syncthreads();
 
@@ -258,15 +261,15 @@ __global__ __launch_bounds__(64) void k_setup64(SetupArgs a) {
 #pragma unroll
     for (int m = 0; m < G; ++m) Mx[lane][m] = w[m];
     __syncthreads();
-    TS *D = static_cast<TS *>(a.tiles) + (size_t)t * E;
+    TS *D = static_cast<TS *>(a.tiles) + (size_t)blockIdx.x * E;
     typedef typename Pair<TS>::type TS2;
     auto diag = [&](int k) -> double {
-        if (lane >= n || 2 * k > n) return 0.0;
-        int jj = lane + k;
+        if (i >= n || 2 * k > n) return 0.0;
+        int jj = i + k;
         if (jj >= n) jj -= n;
         double wv[G];
 #pragma unroll
-        for (int m = 0; m < G; ++m) wv[m] = Mx[jj][m];
+        for (int m = 0; m < G; ++m) wv[m] = Mx[base + jj][m];
         double acc = 0.0;
 #pragma unroll
         for (int m = 0; m < G; ++m) acc += w[m] * wv[m];
@@ -278,12 +281,12 @@ __global__ __launch_bounds__(64) void k_setup64(SetupArgs a) {
         v.y = (TS)diag(k + 1);
         *reinterpret_cast<TS2 *>(D + diag_index(G, k, lane)) = v;
     }
-    if (lane < G / 2) {
+    if (i < G / 2) {
         double v = 0.0;
         if (n == G) {
             double acc = 0.0;
 #pragma unroll
-            for (int m = 0; m < G; ++m) acc += w[m] * Mx[lane + G / 2][m];
+            for (int m = 0; m < G; ++m) acc += w[m] * Mx[base + i + G / 2][m];
             v = acc;
         }
         D[diag_index(G, G / 2, lane)] = (TS)v;
