@@ -157,7 +157,11 @@ typedef struct {
     int32_t max_replacements; /* true-residual restarts (default 3; <0 means none)  */
     int32_t check_every;      /* iterations between convergence polls (default 16) */
     int32_t spmv_lanes;       /* CSR product schedule: 0 = auto, 1,2,..,64 = lanes
-                                 per row, < 0 = row blocks streamed through LDS    */
+                                 per row, -2 = column panels for the iteration's
+                                 product (rows of >= 12 entries on average, n >=
+                                 512; BJP_EINVAL otherwise; auto picks them from
+                                 n >= 2^20 on), other < 0 = row blocks streamed
+                                 through LDS                                      */
     int32_t pad;
     double *history;          /* device, optional, >= max_iter+1 entries: recursive
                                  relative residual after each iteration             */
@@ -173,7 +177,9 @@ typedef struct {
     double rel_res_true;       /* ||b - A x|| / ||b|| recomputed at the end        */
 } bjp_pcg_info_t;
 
-/* Bytes of workspace bjp_pcg_solve needs for an n-row system. */
+/* Bytes of workspace bjp_pcg_solve needs for this matrix (with rows of >= 12
+ * entries on average this includes the column-panel copy of A: 12 bytes per
+ * entry and 100 bytes per row). */
 int bjp_pcg_workspace(const bjp_csr_t *A, size_t *bytes /* host out */);
 
 /* Solve A x = b by preconditioned CG (Hestenes-Stiefel with a symmetric

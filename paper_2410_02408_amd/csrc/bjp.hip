@@ -650,12 +650,35 @@ int bjp_apply(const bjp_precond_t *M, const double *r, double *z, hipStream_t st
     return BJP_OK;
 }
 
+// Column panels (see spmv.hpp) need rows of at least kPanelMeanRow entries
+// on average; they are chosen automatically once the gathered vector is
+// larger than an XCD's L2 could hold (n >= 2^20 rows, 8 MB), or forced with
+// spmv_lanes = -2.
+constexpr int kPanelMeanRow = 12;
+bool panels_possible(const bjp_csr_t *A) {
+    return A->n >= kPanels * 64 && (double)A->nnz >= (double)kPanelMeanRow * A->n;
+}
+bool use_panels(int opt, const bjp_csr_t *A) {
+    if (opt == -2) return panels_possible(A);
+    return opt == 0 && panels_possible(A) && A->n >= (1 << 20);
+}
+int panel_nscan(int n) { return ceil_div(std::max(n, 1), kScanRows); }
+// Panel-major copy of A, its row pointers and the partial products (the
+// per-(panel, row) counts of the build share the partial products' space).
+size_t panel_bytes(const bjp_csr_t *A) {
+    if (!panels_possible(A)) return 0;
+    const size_t n = (size_t)A->n, nnz = (size_t)A->nnz;
+    return al256(sizeof(int32_t) * kPanels * (size_t)panel_nscan(A->n)) + al256(sizeof(int32_t) * kPanels * (n + 1)) +
+           al256(sizeof(int32_t) * nnz) + al256(sizeof(double) * nnz) + al256(sizeof(double) * kPanels * n);
+}
+
 int bjp_pcg_workspace(const bjp_csr_t *A, size_t *bytes) {
     if (!bytes) return BJP_EINVAL;
     *bytes = 0;
     if (check_csr_host(A) != BJP_OK) return BJP_EINVAL;
     const size_t vec = al256(sizeof(double) * (size_t)std::max(A->n, 1));
-    *bytes = 5 * vec + 2 * al256(sizeof(double) * 2 * kMaxRedWG) + 2 * al256(sizeof(PcgState)) + 2 * al256(64);
+    *bytes = 5 * vec + 2 * al256(sizeof(double) * 2 * kMaxRedWG) + 2 * al256(sizeof(PcgState)) + 2 * al256(64) +
+             panel_bytes(A);
     return BJP_OK;
 }
 
@@ -704,8 +727,36 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
     int s = run_validate(A, flags, stream);
     if (s != BJP_OK) return fail(s);
 
-    const int gs = spmv_schedule(o.spmv_lanes, A);
+    // the iteration's product q = A p: column panels or the CSR schedule;
+    // the residual products always take the CSR schedule
+    const bool panels = use_panels(o.spmv_lanes, A);
+    if (o.spmv_lanes == -2 && !panels) return fail(BJP_EINVAL);
+    const int gs = spmv_schedule(o.spmv_lanes == -2 ? 0 : o.spmv_lanes, A);
     const RowLaunch Ls = spmv_shape(n, gs);
+    PanelArgs pa{};
+    const RowLaunch Lf = rows_shape(n);
+    const int panel_grid = kPanels * ceil_div(n, kPanelRowsWG);
+    if (panels) {
+        pa.n = n;
+        pa.width = ceil_div(n, kPanels);
+        pa.rp = A->row_ptr;
+        pa.ci = A->col_idx;
+        pa.val = A->val;
+        pa.nscan = panel_nscan(n);
+        pa.bsum = cv.take<int32_t>((size_t)kPanels * pa.nscan);
+        pa.prp = cv.take<int32_t>((size_t)kPanels * ((size_t)n + 1));
+        pa.pci = cv.take<int32_t>((size_t)A->nnz);
+        pa.pval = cv.take<double>((size_t)A->nnz);
+        pa.Y = cv.take<double>((size_t)kPanels * n);
+        pa.cnt = reinterpret_cast<int32_t *>(pa.Y);
+        const int rgrid = std::min(ceil_div(n, kWG), 4096);
+        hipLaunchKernelGGL(k_panel_count, dim3(rgrid), dim3(kWG), 0, stream, pa);
+        hipLaunchKernelGGL(k_panel_blocksum, dim3(pa.nscan), dim3(kWG), 0, stream, pa);
+        hipLaunchKernelGGL(k_panel_blockscan, dim3(1), dim3(kWG), 0, stream, pa);
+        hipLaunchKernelGGL(k_panel_offsets, dim3(pa.nscan), dim3(kWG), 0, stream, pa);
+        hipLaunchKernelGGL(k_panel_scatter, dim3(rgrid), dim3(kWG), 0, stream, pa);
+        HIP_TRY(hipGetLastError());
+    }
     const RowLaunch La = M ? apply_shape(M) : rows_shape(n);
     const int fill_grid = std::min(ceil_div(n, kWG), 4096);
 
@@ -758,9 +809,11 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
     au.st = st1;
     au.st_out = st;
     au.dec_partials = partials;
-    au.dec_nparts = Ls.grid;
+    au.dec_nparts = panels ? Lf.grid : Ls.grid;
     SpmvArgs su = sa;
     su.st = st1;
+    SpmvArgs suf = su;      // the panel launches' row finish
+    suf.chunk = Lf.chunk;
     FinishArgs fu = fa;
     fu.partials = partials_a;
 
@@ -801,7 +854,12 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
             hipLaunchKernelGGL((k_direction<FIN_PCG_UPDATE_I>), dim3(dir_grid), dim3(kWG), 0, stream, st, st1,
                                partials_a, La.grid, o.history, z, p0, p1, x, n);
         mark(BJP_KERNEL_SPMV, 0);
-        launch_spmv<SPMV_SIGMA>(gs, Ls.grid, su, stream);
+        if (panels) {
+            hipLaunchKernelGGL(k_spmv_panels<SPMV_SIGMA>, dim3(panel_grid), dim3(kWG), 0, stream, su, pa);
+            hipLaunchKernelGGL(k_panel_finish<SPMV_SIGMA>, dim3(Lf.grid), dim3(kWG), 0, stream, suf, pa);
+        } else {
+            launch_spmv<SPMV_SIGMA>(gs, Ls.grid, su, stream);
+        }
         mark(BJP_KERNEL_SPMV, 1);
         mark(BJP_KERNEL_APPLY, 0);
         if (M) launch_apply<APPLY_STEP>(M, La.grid, au, stream);

@@ -359,3 +359,201 @@ __global__ void k_x_finish_clear(PcgState *st) {
 }
 
 }  // namespace bjp
+
+namespace bjp {
+
+// ---------------------------------------------------------------------------
+// Column-panel product for long random-gather rows (the power-law family),
+// whose gathered vector exceeds an XCD's L2: a random 8-byte gather costs an
+// L2 request, and once the vector no longer fits the L2 each one goes on to
+// the last-level cache.  The columns are cut into kPanels contiguous panels
+// and the matrix is copied once per solve panel-major (panel q holds the
+// entries whose column lies in q, row by row, in the order they have in the
+// row).  Workgroup b of the product takes panel b mod kPanels (the
+// workgroups of one panel then run on one XCD, whose L2 holds that slice of
+// the vector) and a chunk of rows, and writes per-panel partial sums;
+// a second launch adds the kPanels partial sums of each row in panel order
+// and finishes the row as the plain product does.  Measured with random
+// columns over a 32 MB vector (4M rows, 143M entries): 2.75 ms for the plain
+// product, 1.62 ms with 8 panels (16 panels: 2.0 ms).
+// ---------------------------------------------------------------------------
+constexpr int kPanels = 8;
+constexpr int kPanelLanes = 8;       // lanes per row within a panel
+constexpr int kPanelRowsWG = 256;    // rows per workgroup of the panel product
+constexpr int kScanRows = 2048;      // rows per workgroup of the offset scan (8 per thread)
+
+struct PanelArgs {
+    int n, width;               // panel q: columns [q*width, (q+1)*width)
+    const int32_t *rp, *ci;     // the caller's CSR
+    const double *val;
+    int32_t *cnt;               // [kPanels][n] entries per (panel, row)
+    int32_t *bsum;              // [kPanels][nscan] per scan block: sums, then offsets
+    int nscan;
+    int32_t *prp;               // [kPanels][n + 1] row pointers into the copy
+    int32_t *pci;               // [nnz] panel-major copy
+    double *pval;
+    double *Y;                  // [kPanels][n] partial products
+};
+
+// Panel of a column (col < n, so the result is < kPanels).
+__device__ __forceinline__ int panel_of(int col, int width) { return col / width; }
+
+// cnt[q][i] = entries of row i in panel q.
+__global__ __launch_bounds__(kWG) void k_panel_count(PanelArgs a) {
+    for (int i = blockIdx.x * kWG + threadIdx.x; i < a.n; i += gridDim.x * kWG) {
+        int c[kPanels];
+#pragma unroll
+        for (int q = 0; q < kPanels; ++q) c[q] = 0;
+        for (int k = a.rp[i]; k < a.rp[i + 1]; ++k) {
+            const int p = panel_of(a.ci[k], a.width);
+#pragma unroll
+            for (int q = 0; q < kPanels; ++q) c[q] += p == q;
+        }
+#pragma unroll
+        for (int q = 0; q < kPanels; ++q) a.cnt[(size_t)q * a.n + i] = c[q];
+    }
+}
+
+// Inclusive prefix sum over the workgroup of one value per thread (fixed order).
+__device__ __forceinline__ int block_scan_incl(int v, int *lds) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int u = __shfl_up(v, off, 64);
+        if (lane >= off) v += u;
+    }
+    if (lane == 63) lds[wave] = v;
+    __syncthreads();
+    int add = 0;
+    for (int w = 0; w < wave; ++w) add += lds[w];
+    __syncthreads();
+    return v + add;
+}
+
+// bsum[q][b] = entries of panel q in the rows of scan block b.
+__global__ __launch_bounds__(kWG) void k_panel_blocksum(PanelArgs a) {
+    __shared__ int lds[kWaves];
+    const int b = blockIdx.x;
+    const int i0 = b * kScanRows + threadIdx.x * (kScanRows / kWG);
+    for (int q = 0; q < kPanels; ++q) {
+        int s = 0;
+        for (int u = 0; u < kScanRows / kWG; ++u) {
+            const int i = i0 + u;
+            if (i < a.n) s += a.cnt[(size_t)q * a.n + i];
+        }
+        const int tot = block_scan_incl(s, lds);
+        if (threadIdx.x == kWG - 1) a.bsum[(size_t)q * a.nscan + b] = tot;
+    }
+}
+
+// One workgroup: bsum[q][b] becomes the offset of scan block b within the
+// copy (panels one after another), and prp[q][n] the end of panel q.
+__global__ __launch_bounds__(kWG) void k_panel_blockscan(PanelArgs a) {
+    __shared__ int lds[kWaves];
+    __shared__ int total;
+    int base = 0;
+    for (int q = 0; q < kPanels; ++q) {
+        int32_t *bs = a.bsum + (size_t)q * a.nscan;
+        for (int b0 = 0; b0 < a.nscan; b0 += kWG) {
+            const int b = b0 + threadIdx.x;
+            const int v = b < a.nscan ? bs[b] : 0;
+            const int incl = block_scan_incl(v, lds);
+            if (b < a.nscan) bs[b] = base + incl - v;
+            if (threadIdx.x == kWG - 1) total = incl;
+            __syncthreads();
+            base += total;
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) a.prp[(size_t)q * (a.n + 1) + a.n] = base;
+    }
+}
+
+// prp[q][i] = start of row i's entries of panel q in the copy.
+__global__ __launch_bounds__(kWG) void k_panel_offsets(PanelArgs a) {
+    __shared__ int lds[kWaves];
+    const int b = blockIdx.x;
+    constexpr int R = kScanRows / kWG;
+    const int i0 = b * kScanRows + threadIdx.x * R;
+    for (int q = 0; q < kPanels; ++q) {
+        int c[R];
+        int s = 0;
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            c[u] = i0 + u < a.n ? a.cnt[(size_t)q * a.n + i0 + u] : 0;
+            s += c[u];
+        }
+        int off = a.bsum[(size_t)q * a.nscan + b] + block_scan_incl(s, lds) - s;
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            if (i0 + u < a.n) a.prp[(size_t)q * (a.n + 1) + i0 + u] = off;
+            off += c[u];
+        }
+    }
+}
+
+// Copies each row's entries to their panels, in row order.
+__global__ __launch_bounds__(kWG) void k_panel_scatter(PanelArgs a) {
+    for (int i = blockIdx.x * kWG + threadIdx.x; i < a.n; i += gridDim.x * kWG) {
+        int pos[kPanels];
+#pragma unroll
+        for (int q = 0; q < kPanels; ++q) pos[q] = a.prp[(size_t)q * (a.n + 1) + i];
+        for (int k = a.rp[i]; k < a.rp[i + 1]; ++k) {
+            const int col = a.ci[k];
+            const int p = panel_of(col, a.width);
+            int at = 0;
+#pragma unroll
+            for (int q = 0; q < kPanels; ++q) {
+                if (p == q) {
+                    at = pos[q];
+                    ++pos[q];
+                }
+            }
+            a.pci[at] = col;
+            a.pval[at] = a.val[k];
+        }
+    }
+}
+
+// Y[q][i] = sum over row i's entries in panel q (of the mode's gathered vector).
+template <int MODE>
+__global__ __launch_bounds__(kWG) void k_spmv_panels(SpmvArgs s, PanelArgs a) {
+    int it = 0;
+    if (!spmv_state<MODE>(s, it)) return;
+    const SpmvMode_<MODE> m(s, it);
+    const int q = blockIdx.x % kPanels, c = blockIdx.x / kPanels;
+    const int32_t *prp = a.prp + (size_t)q * (a.n + 1);
+    const int r0 = c * kPanelRowsWG, r1 = min(r0 + kPanelRowsWG, a.n);
+    const int sub = threadIdx.x % kPanelLanes;
+    // the kPanelLanes lanes of a row share its trip count (the shuffles below)
+    for (int row = r0 + threadIdx.x / kPanelLanes; row < r1; row += kWG / kPanelLanes) {
+        double acc = 0.0;
+        const int ke = prp[row + 1];
+        for (int k = prp[row] + sub; k < ke; k += kPanelLanes)
+            acc += __builtin_nontemporal_load(a.pval + k) * m.gather(__builtin_nontemporal_load(a.pci + k));
+#pragma unroll
+        for (int off = kPanelLanes / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (sub == 0) __builtin_nontemporal_store(acc, a.Y + (size_t)q * a.n + row);
+    }
+}
+
+// Row i's product = the panel partial sums in panel order; then the mode's
+// row finish and the per-workgroup dots, as the plain product.
+template <int MODE>
+__global__ __launch_bounds__(kWG) void k_panel_finish(SpmvArgs s, PanelArgs a) {
+    int it = 0;
+    if (!spmv_state<MODE>(s, it)) return;
+    const SpmvMode_<MODE> m(s, it);
+    const int c = xcd_chunk(blockIdx.x, gridDim.x);
+    const int r0 = c * s.chunk, r1 = min(r0 + s.chunk, a.n);
+    double d0 = 0.0, d1 = 0.0;
+    for (int i = r0 + threadIdx.x; i < r1; i += kWG) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < kPanels; ++q) acc += __builtin_nontemporal_load(a.Y + (size_t)q * a.n + i);
+        m.finish(i, m.own(i), acc, d0, d1);
+    }
+    const double v[2] = {d0, d1};
+    block_partial<2>(v, s.partials);
+}
+
+}  // namespace bjp

@@ -423,3 +423,35 @@ def test_kernel_timer_stride(gpu, stride):
     assert -(-info1.iterations // stride) <= n <= 512
     d = tm.durations_ms()
     assert len(d) == n and all(v > 0 for v in d)
+
+
+PANEL_CASES = [
+    ("powerlaw_16k/32", lambda: w.powerlaw_spd(1 << 14, seed=7), 32, 0),
+    ("powerlaw_4100/16", lambda: w.powerlaw_spd(4100, seed=8, max_offdiag=300), 16, 0),
+    ("random_spd_9000/none", lambda: w.random_spd(9000, np.random.default_rng(12), pairs_per_row=7.0), 0, 0),
+]
+
+
+@pytest.mark.parametrize("name,make,nb,_", PANEL_CASES, ids=[c[0] for c in PANEL_CASES])
+def test_pcg_column_panels(gpu, orc, name, make, nb, _):
+    """The column-panel product (forced with spmv_lanes = -2; rows of the
+    power-law family, ragged panel widths and scan blocks) gives
+    oracle-parity results, the same iteration count as the CSR schedule, and
+    bitwise the same result on a second solve."""
+    print(f"case {name}", flush=True)
+    A = make()
+    b = w.rhs(A.n, 41)
+    info, _ = _pcg_parity(gpu, orc, A, b, nb, spmv_lanes=-2)
+    x1, info1 = gpu.pcg_solve(dev(A), gpu.precondition(dev(A), block_size=nb) if nb else None, b, spmv_lanes=-2)
+    x2, info2 = gpu.pcg_solve(dev(A), gpu.precondition(dev(A), block_size=nb) if nb else None, b, spmv_lanes=-2)
+    assert info1.iterations == info2.iterations and torch.equal(x1, x2)
+    _, info_csr = gpu.pcg_solve(dev(A), gpu.precondition(dev(A), block_size=nb) if nb else None, b)
+    assert abs(info_csr.iterations - info.iterations) <= max(1, int(np.ceil(0.03 * info.iterations)))
+
+
+def test_pcg_column_panels_need_long_rows(gpu):
+    """Forcing column panels on short rows (3D stencil, 7 per row) is an
+    argument error."""
+    W = w.workload("diffusion3d_16")
+    with pytest.raises(gpu.BjpError):
+        gpu.pcg_solve(dev(W.A), None, W.b, spmv_lanes=-2)
