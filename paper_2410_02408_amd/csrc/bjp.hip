@@ -735,9 +735,10 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
     const RowLaunch Ls = spmv_shape(n, gs);
     PanelArgs pa{};
     const RowLaunch Lf = rows_shape(n);
-    const int panel_grid = kPanels * ceil_div(n, kPanelRowsWG);
+    const int panel_grid = kPanels * std::min(ceil_div(n, kPanelRowsWG), 8 * device_cus() / kPanels * 4);
     if (panels) {
         pa.n = n;
+        pa.nnz = A->nnz;
         pa.width = ceil_div(n, kPanels);
         pa.rp = A->row_ptr;
         pa.ci = A->col_idx;
@@ -749,7 +750,7 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
         pa.pval = cv.take<double>((size_t)A->nnz);
         pa.Y = cv.take<double>((size_t)kPanels * n);
         pa.cnt = reinterpret_cast<int32_t *>(pa.Y);
-        const int rgrid = std::min(ceil_div(n, kWG), 4096);
+        const int rgrid = std::min(ceil_div(n, kWG / kBuildLanes), 8192);
         hipLaunchKernelGGL(k_panel_count, dim3(rgrid), dim3(kWG), 0, stream, pa);
         hipLaunchKernelGGL(k_panel_blocksum, dim3(pa.nscan), dim3(kWG), 0, stream, pa);
         hipLaunchKernelGGL(k_panel_blockscan, dim3(1), dim3(kWG), 0, stream, pa);
@@ -887,9 +888,20 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
         return BJP_OK;
     };
 
-    sa.resid_phase = 0;
-    launch_spmv<SPMV_RESID>(gs, Ls.grid, sa, stream);
-    finish<FIN_RESID_START>(fa, Ls.grid, stream);
+    // r = b - A x and its norms (the panel copy serves it too when built)
+    auto resid_product = [&](int phase) {
+        sa.resid_phase = phase;
+        if (panels) {
+            SpmvArgs saf = sa;
+            saf.chunk = Lf.chunk;
+            hipLaunchKernelGGL(k_spmv_panels<SPMV_RESID>, dim3(panel_grid), dim3(kWG), 0, stream, sa, pa);
+            hipLaunchKernelGGL(k_panel_finish<SPMV_RESID>, dim3(Lf.grid), dim3(kWG), 0, stream, saf, pa);
+        } else {
+            launch_spmv<SPMV_RESID>(gs, Ls.grid, sa, stream);
+        }
+        return panels ? Lf.grid : Ls.grid;
+    };
+    finish<FIN_RESID_START>(fa, resid_product(0), stream);
     start_direction();
 
     // Polls overlap the iterations: the next batch is launched before the
@@ -944,9 +956,7 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
         if (h.status != BJP_OK || h.zero_rhs) break;
         // converged on the recursive residual: confirm with the true one
         finish_x();
-        sa.resid_phase = 1;
-        launch_spmv<SPMV_RESID>(gs, Ls.grid, sa, stream);
-        finish<FIN_RESID_TRUE>(fa, Ls.grid, stream);
+        finish<FIN_RESID_TRUE>(fa, resid_product(1), stream);
         if ((s = read_state(h)) != BJP_OK) return fail(s);
         if (h.relres_true <= o.tol) break;
         if (replacements >= o.max_replacements) {
@@ -969,9 +979,7 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
         HIP_TRY(hipStreamSynchronize(stream));
     } else if (status != BJP_OK) {
         finish_x();
-        sa.resid_phase = 1;
-        launch_spmv<SPMV_RESID>(gs, Ls.grid, sa, stream);
-        finish<FIN_RESID_TRUE>(fa, Ls.grid, stream);
+        finish<FIN_RESID_TRUE>(fa, resid_product(1), stream);
         if ((s = read_state(h)) != BJP_OK) return fail(s);
     }
     info->status = status;

@@ -384,6 +384,7 @@ constexpr int kScanRows = 2048;      // rows per workgroup of the offset scan (8
 
 struct PanelArgs {
     int n, width;               // panel q: columns [q*width, (q+1)*width)
+    int nnz;                    // entries of A (bound of the copy)
     const int32_t *rp, *ci;     // the caller's CSR
     const double *val;
     int32_t *cnt;               // [kPanels][n] entries per (panel, row)
@@ -398,19 +399,35 @@ struct PanelArgs {
 // Panel of a column (col < n, so the result is < kPanels).
 __device__ __forceinline__ int panel_of(int col, int width) { return col / width; }
 
+// The build walks each row with a group of kBuildLanes lanes (rows are up
+// to thousands of entries long, so one thread per row would leave a long
+// tail and uncoalesced reads).
+constexpr int kBuildLanes = 16;
+
 // cnt[q][i] = entries of row i in panel q.
 __global__ __launch_bounds__(kWG) void k_panel_count(PanelArgs a) {
-    for (int i = blockIdx.x * kWG + threadIdx.x; i < a.n; i += gridDim.x * kWG) {
+    const int sub = threadIdx.x % kBuildLanes;
+    const int groups = gridDim.x * (kWG / kBuildLanes);
+    for (int i = blockIdx.x * (kWG / kBuildLanes) + threadIdx.x / kBuildLanes; i < a.n; i += groups) {
         int c[kPanels];
 #pragma unroll
         for (int q = 0; q < kPanels; ++q) c[q] = 0;
-        for (int k = a.rp[i]; k < a.rp[i + 1]; ++k) {
+        for (int k = a.rp[i] + sub; k < a.rp[i + 1]; k += kBuildLanes) {
             const int p = panel_of(a.ci[k], a.width);
 #pragma unroll
             for (int q = 0; q < kPanels; ++q) c[q] += p == q;
         }
 #pragma unroll
-        for (int q = 0; q < kPanels; ++q) a.cnt[(size_t)q * a.n + i] = c[q];
+        for (int q = 0; q < kPanels; ++q) {
+#pragma unroll
+            for (int off = kBuildLanes / 2; off > 0; off >>= 1) c[q] += __shfl_xor(c[q], off, 64);
+        }
+        if (sub < kPanels) {
+            int v = 0;
+#pragma unroll
+            for (int q = 0; q < kPanels; ++q) v = sub == q ? c[q] : v;
+            a.cnt[(size_t)sub * a.n + i] = v;
+        }
     }
 }
 
@@ -491,25 +508,37 @@ __global__ __launch_bounds__(kWG) void k_panel_offsets(PanelArgs a) {
     }
 }
 
-// Copies each row's entries to their panels, in row order.
+// Copies each row's entries to their panels, in row order: a group takes
+// kBuildLanes consecutive entries at a time; an entry's place is its panel's
+// next free slot plus the number of lower lanes of the group whose entry
+// falls in the same panel (ballots), so the copy keeps the row's order.
 __global__ __launch_bounds__(kWG) void k_panel_scatter(PanelArgs a) {
-    for (int i = blockIdx.x * kWG + threadIdx.x; i < a.n; i += gridDim.x * kWG) {
+    const int lane = threadIdx.x & 63, sub = threadIdx.x % kBuildLanes;
+    const unsigned long long gmask = ((1ull << kBuildLanes) - 1) << (lane - sub);
+    const unsigned long long below = gmask & ((1ull << lane) - 1);
+    const int groups = gridDim.x * (kWG / kBuildLanes);
+    for (int i = blockIdx.x * (kWG / kBuildLanes) + threadIdx.x / kBuildLanes; i < a.n; i += groups) {
         int pos[kPanels];
 #pragma unroll
         for (int q = 0; q < kPanels; ++q) pos[q] = a.prp[(size_t)q * (a.n + 1) + i];
-        for (int k = a.rp[i]; k < a.rp[i + 1]; ++k) {
-            const int col = a.ci[k];
-            const int p = panel_of(col, a.width);
+        const int ke = a.rp[i + 1];
+        for (int k0 = a.rp[i]; k0 < ke; k0 += kBuildLanes) {
+            const int k = k0 + sub;
+            const bool valid = k < ke;
+            const int col = valid ? a.ci[k] : 0;
+            const double v = valid ? a.val[k] : 0.0;
+            const int p = valid ? panel_of(col, a.width) : -1;
             int at = 0;
 #pragma unroll
             for (int q = 0; q < kPanels; ++q) {
-                if (p == q) {
-                    at = pos[q];
-                    ++pos[q];
-                }
+                const unsigned long long m = __ballot(p == q) & gmask;
+                if (p == q) at = pos[q] + __popcll(m & below);
+                pos[q] += __popcll(m);
             }
-            a.pci[at] = col;
-            a.pval[at] = a.val[k];
+            if (valid && at < a.nnz) {
+                a.pci[at] = col;
+                a.pval[at] = v;
+            }
         }
     }
 }
@@ -520,19 +549,22 @@ __global__ __launch_bounds__(kWG) void k_spmv_panels(SpmvArgs s, PanelArgs a) {
     int it = 0;
     if (!spmv_state<MODE>(s, it)) return;
     const SpmvMode_<MODE> m(s, it);
-    const int q = blockIdx.x % kPanels, c = blockIdx.x / kPanels;
+    const int q = blockIdx.x % kPanels;
     const int32_t *prp = a.prp + (size_t)q * (a.n + 1);
-    const int r0 = c * kPanelRowsWG, r1 = min(r0 + kPanelRowsWG, a.n);
     const int sub = threadIdx.x % kPanelLanes;
-    // the kPanelLanes lanes of a row share its trip count (the shuffles below)
-    for (int row = r0 + threadIdx.x / kPanelLanes; row < r1; row += kWG / kPanelLanes) {
-        double acc = 0.0;
-        const int ke = prp[row + 1];
-        for (int k = prp[row] + sub; k < ke; k += kPanelLanes)
-            acc += __builtin_nontemporal_load(a.pval + k) * m.gather(__builtin_nontemporal_load(a.pci + k));
+    const int nchunks = (a.n + kPanelRowsWG - 1) / kPanelRowsWG, cstride = gridDim.x / kPanels;
+    for (int c = blockIdx.x / kPanels; c < nchunks; c += cstride) {
+        const int r0 = c * kPanelRowsWG, r1 = min(r0 + kPanelRowsWG, a.n);
+        // the kPanelLanes lanes of a row share its trip count (the shuffles below)
+        for (int row = r0 + threadIdx.x / kPanelLanes; row < r1; row += kWG / kPanelLanes) {
+            double acc = 0.0;
+            const int ke = min(prp[row + 1], a.nnz);
+            for (int k = prp[row] + sub; k < ke; k += kPanelLanes)
+                acc += __builtin_nontemporal_load(a.pval + k) * m.gather(__builtin_nontemporal_load(a.pci + k));
 #pragma unroll
-        for (int off = kPanelLanes / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-        if (sub == 0) __builtin_nontemporal_store(acc, a.Y + (size_t)q * a.n + row);
+            for (int off = kPanelLanes / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+            if (sub == 0) __builtin_nontemporal_store(acc, a.Y + (size_t)q * a.n + row);
+        }
     }
 }
 
