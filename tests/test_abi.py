@@ -103,3 +103,23 @@ def test_maximum_sizes_without_gpu(lib):
     for big in [bjp.CsrT(max_dim + 1, 10, 1, 1, 1), bjp.CsrT(10, max_dim + 1, 1, 1, 1)]:
         assert L.bjp_pcg_workspace(C.byref(big), C.byref(n)) == -1
         assert L.bjp_precondition_workspace(C.byref(big), C.byref(spec), 0, C.byref(n)) == -1
+
+
+def test_pcg_workspace_covers_column_panels_without_gpu(lib):
+    """Matrices with rows of >= 12 entries on average (at least 512 rows) get
+    workspace for the column-panel copy of A; shorter rows do not."""
+    from paper_2410_02408_amd import bjp
+
+    L = bjp.load()
+    n = C.c_size_t()
+    short = bjp.CsrT(1 << 20, 7 << 20, 1, 1, 1)
+    long_ = bjp.CsrT(1 << 20, 32 << 20, 1, 1, 1)
+    assert L.bjp_pcg_workspace(C.byref(short), C.byref(n)) == 0
+    base = n.value
+    assert L.bjp_pcg_workspace(C.byref(long_), C.byref(n)) == 0
+    extra = n.value - base
+    # panel-major copy (12 B per entry) + row pointers and partial sums (~100 B per row)
+    assert 12 * (32 << 20) + 96 * (1 << 20) <= extra <= 12 * (32 << 20) + 110 * (1 << 20)
+    small = bjp.CsrT(500, 500 * 20, 1, 1, 1)
+    assert L.bjp_pcg_workspace(C.byref(small), C.byref(n)) == 0
+    assert n.value < 5 * 8 * 512 + 100000
