@@ -455,3 +455,17 @@ def test_pcg_column_panels_need_long_rows(gpu):
     W = w.workload("diffusion3d_16")
     with pytest.raises(gpu.BjpError):
         gpu.pcg_solve(dev(W.A), None, W.b, spmv_lanes=-2)
+
+
+SWEEP_CASES = [(n, nb, lanes) for n, nb in [(513, 7), (777, 16), (1000, 33), (2049, 64), (4099, 1)]
+               for lanes in (-2, -1, 0, 4, 16)]
+
+
+@pytest.mark.parametrize("n,nb,lanes", SWEEP_CASES, ids=[f"n{c[0]}-nb{c[1]}-lanes{c[2]}" for c in SWEEP_CASES])
+def test_pcg_odd_sizes_every_schedule(gpu, orc, n, nb, lanes):
+    """Odd sizes (n not a multiple of the panel count, the scan block or the
+    block size; ragged last blocks) under every product schedule, column
+    panels included, against the oracle."""
+    print(f"case n={n} nb={nb} lanes={lanes}", flush=True)
+    A = w.random_spd(n, np.random.default_rng(n + nb), pairs_per_row=7.0)
+    _pcg_parity(gpu, orc, A, w.rhs(n, n), nb, spmv_lanes=lanes)
