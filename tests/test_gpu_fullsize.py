@@ -163,3 +163,22 @@ def test_fullsize_precision_vs_oracle(gpu, orc, powerlaw):
               f"relative error against the oracle {err:.2e}", flush=True)
         assert abs(info.iterations - ref.iterations) <= 1, (prec, info.iterations, ref.iterations)
         assert err <= 1e-10, (prec, err)
+
+
+def test_fullsize_fp32_store_headline(gpu, orc, big):
+    """FP32-stored inverses on the 128^3 workload: the true residual
+    (recomputed with the oracle's SpMV) reaches 1e-10 as with FP64 storage, in
+    about as many iterations, and the two solutions agree to the accuracy the
+    residual bound allows (kappa(A) ~ 2.6e4 times 1e-10)."""
+    W, A, M = big
+    M32 = gpu.precondition(A, block_size=W.block_size, precision="fp32")
+    x64, i64 = gpu.pcg_solve(A, M, W.b, tol=W.tol)
+    x32, i32 = gpu.pcg_solve(A, M32, W.b, tol=W.tol)
+    assert i32.status == "OK" and abs(i32.iterations - i64.iterations) <= max(2, i64.iterations // 50)
+    x32h = x32.cpu().numpy()
+    res = np.linalg.norm(orc.spmv(W.A, x32h) - W.b) / np.linalg.norm(W.b)
+    assert res <= W.tol
+    err = np.linalg.norm(x32h - x64.cpu().numpy()) / np.linalg.norm(x64.cpu().numpy())
+    print(f"fp32-stored: {i32.iterations} iterations (fp64 {i64.iterations}), true residual {res:.2e}, "
+          f"relative difference from the FP64-stored solution {err:.2e}", flush=True)
+    assert err <= 2.6e4 * W.tol * 10
