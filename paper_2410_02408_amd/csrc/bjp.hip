@@ -257,11 +257,14 @@ void launch_apply(const bjp_precond_t *M, int grid, const ApplyArgs &a, hipStrea
     else launch_apply_t<double, MODE>(M->group, grid, a, s);
 }
 
-// gs = lanes per row of the lane-group schedule, 0 = row-block streaming.
+// gs = lanes per row of the lane-group schedule; 0 = row-block streaming with
+// stages of 4 entries per thread, kStream7 = with stages of 7.
+constexpr int kStream7 = -7;
 template <int MODE>
 void launch_spmv(int gs, int grid, const SpmvArgs &a, hipStream_t s) {
     switch (gs) {
-        case 0: hipLaunchKernelGGL((k_spmv_stream<MODE>), dim3(grid), dim3(kWG), 0, s, a); break;
+        case 0: hipLaunchKernelGGL((k_spmv_stream<MODE, 4>), dim3(grid), dim3(kWG), 0, s, a); break;
+        case kStream7: hipLaunchKernelGGL((k_spmv_stream<MODE, 7>), dim3(grid), dim3(kWG), 0, s, a); break;
         case 1: hipLaunchKernelGGL((k_spmv<1, MODE>), dim3(grid), dim3(kWG), 0, s, a); break;
         case 2: hipLaunchKernelGGL((k_spmv<2, MODE>), dim3(grid), dim3(kWG), 0, s, a); break;
         case 4: hipLaunchKernelGGL((k_spmv<4, MODE>), dim3(grid), dim3(kWG), 0, s, a); break;
@@ -278,7 +281,7 @@ struct RowLaunch {
 };
 
 RowLaunch spmv_shape(int n, int gs) {
-    if (gs == 0) {
+    if (gs <= 0) {
         // whole row blocks per workgroup
         const int blocks = ceil_div(std::max(n, 1), kStreamRows);
         const int per = ceil_div(blocks, kMaxRedWG);
@@ -365,15 +368,19 @@ int auto_lanes(const bjp_csr_t *A) {
 #endif
 // Schedule of the single-system products: row-block streaming (0) for short
 // rows, else the lane-group schedule with auto_lanes lanes.
+// Streaming stage size from the mean row length.
+int stream_schedule(const bjp_csr_t *A) {
+    return A->n > 0 && (double)A->nnz <= 7.0 * A->n ? kStream7 : 0;
+}
 int auto_spmv(const bjp_csr_t *A) {
-    if (A->n > 0 && (double)A->nnz / A->n < BJP_STREAM_MEAN) return 0;
+    if (A->n > 0 && (double)A->nnz / A->n < BJP_STREAM_MEAN) return stream_schedule(A);
     return auto_lanes(A);
 }
 
 // Schedule from the user's option: > 0 lanes per row, < 0 streaming, 0 auto.
 int spmv_schedule(int opt, const bjp_csr_t *A) {
     if (opt > 0) return pow2_at_least(std::min(opt, 64));
-    if (opt < 0) return 0;
+    if (opt < 0) return stream_schedule(A);
     return auto_spmv(A);
 }
 
@@ -495,7 +502,8 @@ size_t batch_tiles_bound(const BatchPlan &P, int min_tile_rows, size_t *nrt, siz
 template <int MODE>
 void launch_spmv_tiles(int gs, int grid, const SpmvArgs &a, const TileSpan &t, hipStream_t s) {
     switch (gs) {
-        case 0: hipLaunchKernelGGL((k_spmv_tiles_stream<MODE>), dim3(grid), dim3(kWG), 0, s, a, t); break;
+        case 0:
+        case kStream7: hipLaunchKernelGGL((k_spmv_tiles_stream<MODE>), dim3(grid), dim3(kWG), 0, s, a, t); break;
         case 1: hipLaunchKernelGGL((k_spmv_tiles<1, MODE>), dim3(grid), dim3(kWG), 0, s, a, t); break;
         case 2: hipLaunchKernelGGL((k_spmv_tiles<2, MODE>), dim3(grid), dim3(kWG), 0, s, a, t); break;
         case 4: hipLaunchKernelGGL((k_spmv_tiles<4, MODE>), dim3(grid), dim3(kWG), 0, s, a, t); break;
