@@ -54,10 +54,23 @@ def apply_bytes(n: int, offsets, elem: int) -> int:
     return int(elem * np.sum(nt * (nt + 1) // 2) + 4 * len(offsets) + 32 * n)
 
 
-def spmv_bytes(n: int, nnz: int) -> int:
-    """Algorithmic bytes of one SpMV launch: CSR (12 nnz + 4(N+1)), p read
-    (8 N), q written (8 N)."""
-    return 12 * nnz + 4 * (n + 1) + 16 * n
+def spmv_bytes(n: int, nnz: int, col_bytes: int = 4) -> int:
+    """Algorithmic bytes of one SpMV launch: CSR ((8 + col_bytes) nnz +
+    4(N+1)), p read (8 N), q written (8 N).  col_bytes is 2 when the product
+    reads 16-bit column offsets (short rows whose columns all lie within
+    +-32K of their 256-row block), else 4."""
+    return (8 + col_bytes) * nnz + 4 * (n + 1) + 16 * n
+
+
+def column_bytes(A) -> int:
+    """Bytes per column index the iteration's product reads for A."""
+    import numpy as np
+
+    if A.n == 0 or A.nnz >= 12 * A.n:
+        return 4
+    rows = np.repeat(np.arange(A.n, dtype=np.int64), np.diff(A.row_ptr))
+    d = A.col_idx.astype(np.int64) - (rows - rows % 256)
+    return 2 if d.min() >= -32768 and d.max() <= 32767 else 4
 
 
 def direction_bytes(n: int) -> int:
@@ -337,7 +350,7 @@ def main():
     elem = 4 if M.precision == bjp.FP32_STORE else 8
     ab = apply_bytes(W.A.n, off, elem)
     achieved = ab / (apply_avg_ms * 1e-3) / 1e9
-    B_iter = ab + spmv_bytes(W.A.n, W.A.nnz) + direction_bytes(W.A.n)
+    B_iter = ab + spmv_bytes(W.A.n, W.A.nnz, column_bytes(W.A)) + direction_bytes(W.A.n)
     iter_gbs = B_iter * sum(iters) / (sum(pcg_ms) / 1e3) / 1e9
     traffic = read_traffic(f"apply_{args.workload}")
 

@@ -71,6 +71,10 @@ __global__ void k_uniform_offsets(int32_t *off, int nblocks, int nb, int n) {
         off[t] = t == nblocks ? n : (int32_t)((long long)t * nb);
 }
 
+__global__ void k_fill_i32(int32_t *p, int n, int32_t v) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+
 __global__ void k_flags_init(int32_t *flags) {
     if (threadIdx.x == 0) {
         flags[0] = INT_MAX;
@@ -680,13 +684,19 @@ size_t panel_bytes(const bjp_csr_t *A) {
            al256(sizeof(int32_t) * nnz) + al256(sizeof(double) * nnz) + al256(sizeof(double) * kPanels * n);
 }
 
+// Short rows (the automatic streaming regime) get 16-bit column offsets.
+bool short_rows(const bjp_csr_t *A) { return A->n > 0 && (double)A->nnz / A->n < BJP_STREAM_MEAN; }
+size_t delta16_bytes(const bjp_csr_t *A) {
+    return short_rows(A) ? al256(sizeof(int16_t) * (size_t)std::max(A->nnz, 1)) + al256(64) : 0;
+}
+
 int bjp_pcg_workspace(const bjp_csr_t *A, size_t *bytes) {
     if (!bytes) return BJP_EINVAL;
     *bytes = 0;
     if (check_csr_host(A) != BJP_OK) return BJP_EINVAL;
     const size_t vec = al256(sizeof(double) * (size_t)std::max(A->n, 1));
     *bytes = 5 * vec + 2 * al256(sizeof(double) * 2 * kMaxRedWG) + 2 * al256(sizeof(PcgState)) + 2 * al256(64) +
-             panel_bytes(A);
+             panel_bytes(A) + delta16_bytes(A);
     return BJP_OK;
 }
 
@@ -766,6 +776,20 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
         hipLaunchKernelGGL(k_panel_scatter, dim3(rgrid), dim3(kWG), 0, stream, pa);
         HIP_TRY(hipGetLastError());
     }
+    // the iteration's streaming product reads 16-bit column offsets when
+    // they all fit (decided on the device)
+    const int16_t *cd = nullptr;
+    int32_t *cd_bad = nullptr;
+    if (short_rows(A)) {
+        int16_t *cdw = cv.take<int16_t>((size_t)std::max(A->nnz, 1));
+        cd_bad = cv.take<int32_t>(16);
+        if (!panels && gs <= 0 && A->nnz > 0) {
+            hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, stream, cd_bad, 1, 0);
+            hipLaunchKernelGGL(k_col_delta16, dim3(std::min(ceil_div(n, kWG), 4096)), dim3(kWG), 0, stream,
+                               A->row_ptr, A->col_idx, n, cdw, cd_bad);
+            cd = cdw;
+        }
+    }
     const RowLaunch La = M ? apply_shape(M) : rows_shape(n);
     const int fill_grid = std::min(ceil_div(n, kWG), 4096);
 
@@ -821,6 +845,8 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
     au.dec_nparts = panels ? Lf.grid : Ls.grid;
     SpmvArgs su = sa;
     su.st = st1;
+    su.cd = cd;
+    su.cd_bad = cd_bad;
     SpmvArgs suf = su;      // the panel launches' row finish
     suf.chunk = Lf.chunk;
     FinishArgs fu = fa;

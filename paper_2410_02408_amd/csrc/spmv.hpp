@@ -54,6 +54,11 @@ struct SpmvArgs {
     double *w;              // LANCZOS: w = A v_j
     int has_m;
     double *partials;       // per-workgroup dots (see the modes)
+    // optional for the row-block streaming schedule: column indices stored as
+    // 16-bit offsets from the first row of their 256-row block (cd), used
+    // when *cd_bad == 0 (every offset fitted)
+    const int16_t *cd;
+    const int32_t *cd_bad;
 };
 
 // CSR values and column indices are streamed once per product.  Loaded
@@ -212,7 +217,7 @@ constexpr int kStreamRows = kWG;
 constexpr int kStreamCap = BJP_STREAM_CAP;
 constexpr int kStreamPer = kStreamCap / kWG;
 
-template <int MODE, bool NT = false, int PER = kStreamPer>
+template <int MODE, bool NT = false, int PER = kStreamPer, bool CD = false>
 __device__ __forceinline__ void spmv_stream_rows(const SpmvArgs &a, int it, int r0, int r1, double &d0,
                                                  double &d1) {
     constexpr int CAP = PER * kWG;   // entries per stage
@@ -221,6 +226,7 @@ __device__ __forceinline__ void spmv_stream_rows(const SpmvArgs &a, int it, int 
     const SpmvMode_<MODE> m(a, it);
     const int32_t *__restrict__ rp = a.rp;
     const int32_t *__restrict__ ci = a.ci;
+    const int16_t *__restrict__ cd = a.cd;
     const double *__restrict__ val = a.val;
     for (int b0 = r0; b0 < r1; b0 += kStreamRows) {
         const int b1 = min(b0 + kStreamRows, r1);
@@ -238,7 +244,8 @@ __device__ __forceinline__ void spmv_stream_rows(const SpmvArgs &a, int it, int 
             for (int j = 0; j < PER; ++j) {
                 const int k = c0 + j * kWG + tid;
                 const int kc = k < c1 ? k : c0;
-                col[j] = csr_load<NT>(ci + kc);
+                if constexpr (CD) col[j] = b0 + (int)csr_load<NT>(cd + kc);
+                else col[j] = csr_load<NT>(ci + kc);
                 vv[j] = csr_load<NT>(val + kc);
             }
 #pragma unroll
@@ -287,7 +294,8 @@ __global__ __launch_bounds__(kWG) void k_spmv_stream(SpmvArgs a) {
     const int r0 = c * a.chunk;
     const int r1 = min(r0 + a.chunk, a.n);
     double d0 = 0.0, d1 = 0.0;
-    spmv_stream_rows<MODE, false, PER>(a, it, r0, r1, d0, d1);
+    if (a.cd != nullptr && *a.cd_bad == 0) spmv_stream_rows<MODE, false, PER, true>(a, it, r0, r1, d0, d1);
+    else spmv_stream_rows<MODE, false, PER, false>(a, it, r0, r1, d0, d1);
     const double v[2] = {d0, d1};
     block_partial<2>(v, a.partials);
 }
@@ -365,6 +373,28 @@ __global__ void k_x_finish_clear(PcgState *st) {
 }  // namespace bjp
 
 namespace bjp {
+
+// Column indices as 16-bit offsets from the first row of the entry's 256-row
+// block (the streaming schedule's block): for banded matrices such as 3D
+// stencils every offset fits, and the product then reads 2 instead of 4 bytes
+// per entry for its columns (measured at 128^3: 37.1 -> 34.9 us per product).
+// The choice between the two is made per launch from *bad, outside the
+// unrolled loads (a select between them had the compiler issue both).
+// *bad is set when some offset does not fit; the product then reads the
+// 32-bit indices.
+__global__ __launch_bounds__(kWG) void k_col_delta16(const int32_t *rp, const int32_t *ci, int n, int16_t *cd,
+                                                    int32_t *bad) {
+    for (int i = blockIdx.x * kWG + threadIdx.x; i < n; i += gridDim.x * kWG) {
+        const int b0 = i - i % kStreamRows;
+        bool fits = true;
+        for (int k = rp[i]; k < rp[i + 1]; ++k) {
+            const int d = ci[k] - b0;
+            fits = fits && d >= -32768 && d <= 32767;
+            cd[k] = (int16_t)d;
+        }
+        if (!fits) atomicMax(bad, 1);
+    }
+}
 
 // ---------------------------------------------------------------------------
 // Column-panel product for long random-gather rows (the power-law family),
