@@ -469,3 +469,15 @@ def test_pcg_odd_sizes_every_schedule(gpu, orc, n, nb, lanes):
     print(f"case n={n} nb={nb} lanes={lanes}", flush=True)
     A = w.random_spd(n, np.random.default_rng(n + nb), pairs_per_row=7.0)
     _pcg_parity(gpu, orc, A, w.rhs(n, n), nb, spmv_lanes=lanes)
+
+
+def test_pcg_short_rows_far_columns(gpu, orc):
+    """Short rows whose columns lie far from their row block (random pairs over
+    100,000 rows): the 16-bit column offsets do not fit, the product falls back
+    to the 32-bit indices, and the solve still matches the oracle."""
+    A = w.random_spd(100000, np.random.default_rng(21), pairs_per_row=3.0)
+    assert A.nnz < 12 * A.n
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    d = A.col_idx.astype(np.int64) - (rows - rows % 256)
+    assert d.max() > 32767 or d.min() < -32768
+    _pcg_parity(gpu, orc, A, w.rhs(A.n, 22), 16)
