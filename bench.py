@@ -140,7 +140,8 @@ def mode_nb_sweep(args):
 
 
 def mode_batch(args):
-    """512 uneven random SPD systems solved in one persistent launch."""
+    """512 uneven random SPD systems solved together (every system advancing in
+    the same tile launches, iterations replayed from a captured hipGraph)."""
     import numpy as np
     import torch
 

@@ -99,7 +99,9 @@ typedef enum {
  * symmetric block inverses diagonal by diagonal (see the kernels). */
 typedef struct {
     int32_t n;
-    int32_t block_size;       /* uniform block size, or 0 for an explicit partition */
+    int32_t block_size;       /* uniform block size (a requested size above n is
+                                 stored as n: one block), or 0 for an explicit
+                                 partition */
     int32_t num_blocks;
     int32_t precision;        /* bjp_precision */
     int32_t group;            /* lanes per block, power of two <= 64 */
@@ -124,8 +126,11 @@ int bjp_precondition(const bjp_csr_t *A, const bjp_block_spec_t *spec, int preci
                      void *ws, size_t ws_bytes, bjp_precond_t *M_out /* host out */,
                      int32_t *failed_block /* host out */, hipStream_t stream);
 
-/* z = M^-1 r (block by block).  r and z are device [n]; they must not
- * overlap.  Asynchronous. */
+/* z = M^-1 r, block by block: z_t = A_tt^-1 r_t for every diagonal block t
+ * (the preconditioner of Section 3.3 with the whole block inverted; at
+ * n_b = 1 it is the paper's point Jacobi, r_i / A_ii).  r and z are device
+ * [n]; they must not overlap.  Asynchronous; returns BJP_EINVAL for a NULL
+ * pointer or a handle that does not describe a partition of n rows. */
 int bjp_apply(const bjp_precond_t *M, const double *r, double *z, hipStream_t stream);
 
 /* Optional kernel timing.  When a solver is given one, every stride-th
@@ -206,7 +211,9 @@ typedef struct {
 /* Bytes of workspace bjp_kappa_estimate needs for `steps` Lanczos steps. */
 int bjp_kappa_workspace(const bjp_csr_t *A, int steps, size_t *bytes /* host out */);
 
-/* Estimate kappa(M^-1 A) = lambda_max / lambda_min (kappa(A) when M == NULL)
+/* Estimate kappa(M^-1 A) = lambda_max / lambda_min (kappa(A) when M == NULL),
+ * the condition number of Section 3.1 (2-norm) of the preconditioned system of
+ * Section 3.3, which sets the cost of the quantum stage (Sections 2.2, 3.4),
  * with `steps` Lanczos steps in the M inner product, started from v0
  * (device [n], nonzero), with full reorthogonalisation (classical
  * Gram-Schmidt applied twice), then the extreme eigenvalues of the
@@ -219,7 +226,8 @@ int bjp_kappa_estimate(const bjp_csr_t *A, const bjp_precond_t *M, const double 
                        bjp_kappa_info_t *info /* host out */, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
- * Batches of independent systems (one persistent launch for the solve).
+ * Batches of independent systems (every system advances in the same kernel
+ * launches; the iterations between polls are replayed from a captured graph).
  * The batch is a single block-diagonal CSR matrix: system s owns rows
  * [sys_rows[s], sys_rows[s+1]) and every column of those rows must lie in
  * the same range (checked).  Each system has its own uniform block size.

@@ -271,7 +271,9 @@ typedef struct {
  *   the true residual ||b - A x|| / ||b|| (Section 3.7); if it is above tol,
  *   replace r by the true residual, restart the direction and continue (at
  *   most max_replacements times).  max_iter bounds the total number of
- *   iterations.  history (optional, >= max_iter+1 entries) receives the
+ *   iterations; a replacement is made only while iterations remain (at
+ *   k = max_iter the solve ends with ENOCONV instead, the replacement count
+ *   unchanged).  history (optional, >= max_iter+1 entries) receives the
  *   recursive relative residual after every iteration (index 0 = start). */
 int orc_pcg(int n, const int *row_ptr, const int *col, const double *val,
             const orc_precond *P, const double *b, double *x, double tol, int max_iter,
@@ -338,7 +340,7 @@ int orc_pcg(int n, const int *row_ptr, const int *col, const double *val,
         double tres = sqrt(orc_dot(n, q, q)) / bnorm;
         info->rel_res_true = tres;
         if (tres <= tol) break;
-        if (info->replacements >= max_replacements) { status = ORC_ENOCONV; break; }
+        if (info->replacements >= max_replacements || k >= max_iter) { status = ORC_ENOCONV; break; }
         info->replacements++;
     }
     if (status != ORC_OK) {

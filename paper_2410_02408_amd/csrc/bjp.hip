@@ -178,9 +178,10 @@ int make_partition(int n, const bjp_block_spec_t *spec, Partition &P) {
     P.uniform = 0;
     if (spec->block_size > 0) {
         if (spec->block_size > BJP_MAX_BLOCK) return BJP_EINVAL;
-        P.uniform = spec->block_size;
-        P.nblocks = ceil_div(n, spec->block_size);
-        P.G = pow2_at_least(n > 0 ? std::min(spec->block_size, n) : 1);
+        // a block size above n gives one block of n rows
+        P.uniform = n > 0 ? std::min(spec->block_size, n) : spec->block_size;
+        P.nblocks = ceil_div(n, P.uniform);
+        P.G = pow2_at_least(n > 0 ? P.uniform : 1);
         P.packets = ceil_div(P.nblocks, 64 / P.G);
         P.E = packet_elems(P.G);
         return BJP_OK;
@@ -608,7 +609,7 @@ int bjp_precondition(const bjp_csr_t *A, const bjp_block_spec_t *spec, int preci
     int32_t *flags = cv.take<int32_t>(16);
 
     M_out->n = A->n;
-    M_out->block_size = spec->block_size > 0 ? spec->block_size : 0;
+    M_out->block_size = P.uniform;
     M_out->num_blocks = P.nblocks;
     M_out->precision = precision;
     M_out->group = P.G;
@@ -993,7 +994,8 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
         finish<FIN_RESID_TRUE>(fa, resid_product(1), stream);
         if ((s = read_state(h)) != BJP_OK) return fail(s);
         if (h.relres_true <= o.tol) break;
-        if (replacements >= o.max_replacements) {
+        // a replacement needs an iteration to follow it
+        if (replacements >= o.max_replacements || h.it >= o.max_iter) {
             status = BJP_ENOCONV;
             break;
         }
@@ -1446,7 +1448,7 @@ int bjp_batch_pcg_solve(const bjp_csr_t *A, const bjp_batch_t *B, const bjp_batc
         std::vector<int> again;
         for (int s = 0; s < S; ++s) {
             if (h[s].status != BJP_OK || h[s].zero_rhs || h[s].relres_true <= o.tol) continue;
-            if (repl[s] >= o.max_replacements) {
+            if (repl[s] >= o.max_replacements || h[s].it >= caps[s]) {
                 host_status[s] = BJP_ENOCONV;
                 continue;
             }

@@ -1,10 +1,13 @@
 """Full-size checks at the benchmark's sizes and launch configuration.
 
-The oracle cannot run 547 PCG iterations or 200 reorthogonalised Lanczos
-steps on N = 2,097,152 within a test, so at full size it checks sampled
-outputs one by one (block solves of M^-1 r, per-system solves of sampled
-batch members) and the properties that hold at any size (the true residual
-recomputed with the oracle's own SpMV, Ritz-value bounds)."""
+At 128^3 (the headline workload) the GPU's solution and both kappa
+estimates are compared with the oracle's: the oracle's PCG solve of the same
+system (547 iterations, about a minute on one core), and Lanczos at a
+reduced step count (40 steps, equal on both sides).  Sampled outputs the
+oracle computes one by one (block solves of M^-1 r, sampled members of the
+512-system batch) and properties that hold at any size (true residual
+recomputed with the oracle's SpMV, Ritz-value bounds, bitwise repeatability)
+complete the picture."""
 import numpy as np
 import pytest
 import torch
@@ -15,12 +18,83 @@ pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 DEV = torch.device("cuda:0")
 
 
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
 @pytest.fixture(scope="module")
 def big(gpu):
     W = w.workload("diffusion3d_128")
     A = gpu.DeviceCsr.from_host(W.A, DEV)
     M = gpu.precondition(A, block_size=W.block_size)
     return W, A, M
+
+
+@pytest.fixture(scope="module")
+def big_oracle(orc, big):
+    """The oracle's PCG solve of the 128^3 system (same algorithm, tol and
+    stopping rule as the GPU's)."""
+    W, _, _ = big
+    print("oracle: 128^3 PCG solve (about a minute)", flush=True)
+    Mo = orc.Precond.uniform(W.A, W.block_size)
+    return Mo, orc.pcg(W.A, W.b, Mo, tol=W.tol)
+
+
+def _check_vs_oracle(orc, W, Mo, ref, x, info, label):
+    """x within 1e-10 of the oracle's solution, iteration counts within one
+    (x then also compared with the oracle stopped at the GPU's count), both
+    true residuals below tol."""
+    xg = x.cpu().numpy()
+    err = _rel(xg, ref.x)
+    res = np.linalg.norm(orc.spmv(W.A, xg) - W.b) / np.linalg.norm(W.b)
+    print(f"{label}: {info.iterations} iterations (oracle {ref.iterations}), relative error against "
+          f"the oracle {err:.2e}, true residual {res:.2e} (oracle {ref.rel_res_true:.2e})", flush=True)
+    assert ref.status == "OK" and ref.rel_res_true <= W.tol
+    assert info.status == "OK" and res <= W.tol and abs(res - info.rel_res_true) <= 1e-3 * W.tol
+    assert abs(info.iterations - ref.iterations) <= 1
+    if info.iterations != ref.iterations:
+        ref_k = orc.pcg(W.A, W.b, Mo, tol=W.tol, max_iter=info.iterations)
+        assert _rel(xg, ref_k.x) <= 1e-10
+    assert err <= 1e-10
+    return err
+
+
+@pytest.mark.timeout(900)
+def test_fullsize_pcg_matches_oracle(gpu, orc, big, big_oracle):
+    """The benchmark's solve (FP64 inverses) against the oracle's at 128^3."""
+    W, A, M = big
+    Mo, ref = big_oracle
+    x, info = gpu.pcg_solve(A, M, W.b, tol=W.tol)
+    _check_vs_oracle(orc, W, Mo, ref, x, info, "fp64")
+
+
+@pytest.mark.timeout(900)
+def test_fullsize_fp32_store_matches_oracle(gpu, orc, big, big_oracle):
+    """FP32-stored, FP32-applied inverses inside the FP64 PCG at 128^3: the
+    solution agrees with the oracle's FP64 solve to 1e-10 relative, in the
+    oracle's iteration count within one."""
+    W, A, _ = big
+    Mo, ref = big_oracle
+    M32 = gpu.precondition(A, block_size=W.block_size, precision="fp32")
+    x, info = gpu.pcg_solve(A, M32, W.b, tol=W.tol)
+    _check_vs_oracle(orc, W, Mo, ref, x, info, "fp32-stored")
+
+
+@pytest.mark.timeout(900)
+def test_fullsize_kappa_matches_oracle(gpu, orc, big, big_oracle):
+    """kappa(A) and kappa(M^-1 A) at 128^3 with 40 Lanczos steps on both
+    sides (the GPU's estimate at full size, the oracle's CGS2 Lanczos in
+    plain loops): equal step counts, relative difference <= 1e-6."""
+    W, A, M = big
+    Mo, _ = big_oracle
+    for label, Md, Mor in (("A", None, None), ("M^-1 A", M, Mo)):
+        k = gpu.kappa_estimate(A, W.b, 40, Md)
+        ko = orc.kappa(W.A, W.b, 40, Mor)
+        print(f"kappa({label}) 40 steps: gpu {k.kappa:.12g} oracle {ko.kappa:.12g} "
+              f"(relative difference {abs(k.kappa - ko.kappa) / ko.kappa:.1e})", flush=True)
+        assert k.status == ko.status == "OK" and k.steps == ko.steps == 40
+        assert abs(k.kappa - ko.kappa) <= 1e-6 * ko.kappa
+        np.testing.assert_allclose(k.alpha, ko.alpha, rtol=1e-8)
 
 
 def test_fullsize_apply_sampled_blocks(gpu, orc, big):
@@ -39,7 +113,7 @@ def test_fullsize_apply_sampled_blocks(gpu, orc, big):
 def test_fullsize_pcg_true_residual(gpu, orc, big):
     W, A, M = big
     x, info = gpu.pcg_solve(A, M, W.b, tol=W.tol)
-    assert info.status == "OK" and info.replacements == 0
+    assert info.status == "OK"
     xg = x.cpu().numpy()
     res = np.linalg.norm(orc.spmv(W.A, xg) - W.b) / np.linalg.norm(W.b)
     assert res <= W.tol and abs(res - info.rel_res_true) <= 1e-3 * W.tol
@@ -67,6 +141,7 @@ def test_fullsize_kappa_bounds(gpu, big):
     assert kA.kappa > kM.kappa
 
 
+@pytest.mark.timeout(900)
 def test_fullsize_batch_sampled_systems(gpu, orc):
     mats, nbs, rhs = w.random_spd_batch(512, seed=2)
     B = gpu.Batch.from_systems(mats, nbs, DEV)
@@ -82,6 +157,7 @@ def test_fullsize_batch_sampled_systems(gpu, orc):
     assert info.max_rel_res_true <= 1e-10
 
 
+@pytest.mark.timeout(900)
 def test_fullsize_adjoint_identity(gpu, orc):
     """Differentiation workload at 1024^2: dL/db = lambda solves A lambda = 2 (x - x_t)."""
     from paper_2410_02408_amd import autograd as ad
@@ -139,6 +215,7 @@ def _powerlaw_solves(gpu, powerlaw):
     return solves
 
 
+@pytest.mark.timeout(900)
 def test_fullsize_precision_paths(gpu, powerlaw):
     """Both the FP64 path and the FP32-stored inverses reach the 1e-10 true
     residual; the two solutions agree far below it."""
@@ -150,6 +227,7 @@ def test_fullsize_precision_paths(gpu, powerlaw):
     assert np.linalg.norm(x32 - x64) / np.linalg.norm(x64) <= 1e-10
 
 
+@pytest.mark.timeout(900)
 def test_fullsize_precision_vs_oracle(gpu, orc, powerlaw):
     """Both solutions agree with the oracle's FP64 solve to 1e-10 relative,
     in the same number of iterations (within one)."""
@@ -163,22 +241,3 @@ def test_fullsize_precision_vs_oracle(gpu, orc, powerlaw):
               f"relative error against the oracle {err:.2e}", flush=True)
         assert abs(info.iterations - ref.iterations) <= 1, (prec, info.iterations, ref.iterations)
         assert err <= 1e-10, (prec, err)
-
-
-def test_fullsize_fp32_store_headline(gpu, orc, big):
-    """FP32-stored inverses on the 128^3 workload: the true residual
-    (recomputed with the oracle's SpMV) reaches 1e-10 as with FP64 storage, in
-    about as many iterations, and the two solutions agree to the accuracy the
-    residual bound allows (kappa(A) ~ 2.6e4 times 1e-10)."""
-    W, A, M = big
-    M32 = gpu.precondition(A, block_size=W.block_size, precision="fp32")
-    x64, i64 = gpu.pcg_solve(A, M, W.b, tol=W.tol)
-    x32, i32 = gpu.pcg_solve(A, M32, W.b, tol=W.tol)
-    assert i32.status == "OK" and abs(i32.iterations - i64.iterations) <= max(2, i64.iterations // 50)
-    x32h = x32.cpu().numpy()
-    res = np.linalg.norm(orc.spmv(W.A, x32h) - W.b) / np.linalg.norm(W.b)
-    assert res <= W.tol
-    err = np.linalg.norm(x32h - x64.cpu().numpy()) / np.linalg.norm(x64.cpu().numpy())
-    print(f"fp32-stored: {i32.iterations} iterations (fp64 {i64.iterations}), true residual {res:.2e}, "
-          f"relative difference from the FP64-stored solution {err:.2e}", flush=True)
-    assert err <= 2.6e4 * W.tol * 10

@@ -155,25 +155,43 @@ def test_malformed_csr_rejected(gpu):
     assert e.value.status == "ENONFINITE"
 
 
-def _pcg_parity(gpu, orc, A, b, nb, tol=1e-10, it_slack=None, **kw):
-    """Same algorithm and stopping rule on both sides.  x must agree with the
-    oracle's converged solution to 1e-10 and both true residuals must be
-    below tol.  Iteration counts: finite-precision CG loses orthogonality at
-    a rate set by rounding, so on ill-conditioned systems two correct
-    implementations that round differently need slightly different numbers
-    of steps; the bar is +-1 for the small workload (it_slack=1) and +-3%
-    otherwise."""
+# Cases whose iteration count may differ from the oracle's by more than one,
+# with the bar and the difference observed on the GPU.  Finite-precision CG
+# loses orthogonality at a rate set by rounding, so on ill-conditioned
+# systems two correct implementations that round differently can take a few
+# more or fewer steps (Greenbaum & Strakos 1992); x still agrees to 1e-10.
+WIDE_ITERATION_BAR = {
+    "diffusion3d_16/none": 8,   # plain CG, kappa(A) ~ 1e4: observed 352 (GPU) vs 359 (oracle)
+}
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _pcg_parity(gpu, orc, A, b, nb, tol=1e-10, case=None, **kw):
+    """Same algorithm and stopping rule on both sides.  Pass if the iteration
+    counts differ by at most one (or the case's listed bar), x agrees with
+    the oracle's solution to 1e-10 relative (with the oracle stopped at the
+    GPU's count when the counts differ) and both true residuals are below
+    tol."""
     Md = gpu.precondition(dev(A), block_size=nb) if nb else None
     Mo = orc.Precond.uniform(A, nb) if nb else None
     x, info = gpu.pcg_solve(dev(A), Md, b, tol=tol, **kw)
     ref = orc.pcg(A, b, Mo, tol=tol)
     xg = x.cpu().numpy()
     true_res = np.linalg.norm(orc.spmv(A, xg) - b) / np.linalg.norm(b)
-    err = np.linalg.norm(xg - ref.x) / np.linalg.norm(ref.x)
-    print(f"  it gpu {info.iterations} oracle {ref.iterations} err {err:.2e} res {true_res:.2e}")
+    err = _rel(xg, ref.x)
+    d = info.iterations - ref.iterations
+    print(f"  it gpu {info.iterations} oracle {ref.iterations} (delta {d}) err {err:.2e} res {true_res:.2e}",
+          flush=True)
     assert info.status == "OK" and ref.status == "OK"
-    slack = it_slack if it_slack is not None else max(1, int(np.ceil(0.03 * ref.iterations)))
-    assert abs(info.iterations - ref.iterations) <= slack
+    assert abs(d) <= WIDE_ITERATION_BAR.get(case, 1), (case, info.iterations, ref.iterations)
+    if d != 0:
+        ref_k = orc.pcg(A, b, Mo, tol=tol, max_iter=info.iterations)
+        err_k = _rel(xg, ref_k.x)
+        print(f"  oracle stopped at {ref_k.iterations}: err {err_k:.2e}", flush=True)
+        assert err_k <= 1e-10
     assert true_res <= tol and info.rel_res_true <= tol
     assert abs(info.rel_res_true - true_res) <= 1e-3 * tol
     assert err <= 1e-10
@@ -183,7 +201,7 @@ def _pcg_parity(gpu, orc, A, b, nb, tol=1e-10, it_slack=None, **kw):
 def test_pcg_small_workload_exact_count(gpu, orc):
     """2D Poisson 32x32, blocks of 16: iteration count within one of the oracle."""
     W = w.workload("poisson2d_32")
-    _pcg_parity(gpu, orc, W.A, W.b, 16, it_slack=1)
+    _pcg_parity(gpu, orc, W.A, W.b, 16)
 
 
 PCG_CASES = [
@@ -200,12 +218,12 @@ PCG_CASES = [
 def test_pcg_matches_oracle(gpu, orc, name, make, nb):
     print(f"case {name}", flush=True)
     W = make()
-    _pcg_parity(gpu, orc, W.A, W.b, nb)
+    _pcg_parity(gpu, orc, W.A, W.b, nb, case=name)
 
 
 def test_pcg_random_spd_ragged(gpu, orc):
     A = w.random_spd(5000, np.random.default_rng(10))
-    _pcg_parity(gpu, orc, A, w.rhs(A.n, 34), 32)
+    _pcg_parity(gpu, orc, A, w.rhs(A.n, 34), 32, case="random_spd_5000/32")
 
 
 @pytest.mark.parametrize("lanes", [-1, 1, 2, 4, 8, 16, 32, 64])
@@ -213,7 +231,7 @@ def test_pcg_schedules_agree(gpu, orc, lanes):
     """Every SpMV schedule (row-block streaming, every lane-group width)
     gives oracle-parity results."""
     W = w.workload("diffusion3d_16")
-    _pcg_parity(gpu, orc, W.A, W.b, 64, spmv_lanes=lanes)
+    _pcg_parity(gpu, orc, W.A, W.b, 64, case="diffusion3d_16/64", spmv_lanes=lanes)
 
 
 def test_pcg_single_block_one_iteration(gpu):
@@ -366,7 +384,8 @@ def test_pcg_warm_start_matches_oracle(gpu, orc):
     x, info = gpu.pcg_solve(dev(W.A), M, W.b, x0=x0)
     ref = orc.pcg(W.A, W.b, orc.Precond.uniform(W.A, 64), x0=x0)
     assert info.status == ref.status == "OK"
-    assert abs(info.iterations - ref.iterations) <= max(1, int(np.ceil(0.03 * ref.iterations)))
+    print(f"  it gpu {info.iterations} oracle {ref.iterations}", flush=True)
+    assert abs(info.iterations - ref.iterations) <= WIDE_ITERATION_BAR.get("diffusion3d_16/64 warm", 1)
     assert np.linalg.norm(x.cpu().numpy() - ref.x) / np.linalg.norm(ref.x) <= 1e-10
 
 
@@ -389,7 +408,7 @@ def test_pcg_streaming_long_and_empty_rows(gpu, orc):
     assert np.diff(A.row_ptr).max() > 2048 and A.nnz / n < 12
     b = w.rhs(n, 23)
     for lanes in (-1, 0):
-        _pcg_parity(gpu, orc, A, b, 16, spmv_lanes=lanes)
+        _pcg_parity(gpu, orc, A, b, 16, case="hub_4000/16", spmv_lanes=lanes)
 
 
 def test_torch_sparse_csr_input(gpu):
@@ -441,12 +460,13 @@ def test_pcg_column_panels(gpu, orc, name, make, nb, _):
     print(f"case {name}", flush=True)
     A = make()
     b = w.rhs(A.n, 41)
-    info, _ = _pcg_parity(gpu, orc, A, b, nb, spmv_lanes=-2)
+    info, _ = _pcg_parity(gpu, orc, A, b, nb, case=name, spmv_lanes=-2)
     x1, info1 = gpu.pcg_solve(dev(A), gpu.precondition(dev(A), block_size=nb) if nb else None, b, spmv_lanes=-2)
     x2, info2 = gpu.pcg_solve(dev(A), gpu.precondition(dev(A), block_size=nb) if nb else None, b, spmv_lanes=-2)
     assert info1.iterations == info2.iterations and torch.equal(x1, x2)
     _, info_csr = gpu.pcg_solve(dev(A), gpu.precondition(dev(A), block_size=nb) if nb else None, b)
-    assert abs(info_csr.iterations - info.iterations) <= max(1, int(np.ceil(0.03 * info.iterations)))
+    print(f"  csr schedule: {info_csr.iterations} iterations", flush=True)
+    assert abs(info_csr.iterations - info.iterations) <= 2 * WIDE_ITERATION_BAR.get(name, 1)
 
 
 def test_pcg_column_panels_need_long_rows(gpu):
@@ -468,7 +488,7 @@ def test_pcg_odd_sizes_every_schedule(gpu, orc, n, nb, lanes):
     panels included, against the oracle."""
     print(f"case n={n} nb={nb} lanes={lanes}", flush=True)
     A = w.random_spd(n, np.random.default_rng(n + nb), pairs_per_row=7.0)
-    _pcg_parity(gpu, orc, A, w.rhs(n, n), nb, spmv_lanes=lanes)
+    _pcg_parity(gpu, orc, A, w.rhs(n, n), nb, case=f"odd_{n}/{nb}", spmv_lanes=lanes)
 
 
 def test_pcg_short_rows_far_columns(gpu, orc):
@@ -480,4 +500,48 @@ def test_pcg_short_rows_far_columns(gpu, orc):
     rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
     d = A.col_idx.astype(np.int64) - (rows - rows % 256)
     assert d.max() > 32767 or d.min() < -32768
-    _pcg_parity(gpu, orc, A, w.rhs(A.n, 22), 16)
+    _pcg_parity(gpu, orc, A, w.rhs(A.n, 22), 16, case="random_spd_100000/16")
+
+
+def split_and_shuffle(A, seed):
+    """The same operator stored with every entry split into two duplicates
+    (u a and (1 - u) a, u in [0.25, 0.75) chosen per unordered pair so A
+    stays symmetric) and each row's entries in random order: the CSR the C
+    ABI promises to accept (duplicates summed, unsorted columns)."""
+    rows = np.repeat(np.arange(A.n, dtype=np.int64), np.diff(A.row_ptr))
+    cols = A.col_idx.astype(np.int64)
+    lo, hi = np.minimum(rows, cols), np.maximum(rows, cols)
+    u = 0.25 + 0.5 * (((lo * 2654435761 + hi * 40503) % 1000) / 1000.0)
+    r2 = np.concatenate([rows, rows])
+    c2 = np.concatenate([cols, cols])
+    v2 = np.concatenate([A.val * u, A.val * (1.0 - u)])
+    order = np.lexsort((np.random.default_rng(seed).random(len(r2)), r2))
+    rp = np.zeros(A.n + 1, np.int64)
+    rp[1:] = np.cumsum(np.bincount(r2, minlength=A.n))
+    return w.CsrMatrix(A.n, rp.astype(np.int32), c2[order].astype(np.int32), v2[order])
+
+
+DUP_CASES = [("random_spd_3000 dup", lambda: w.random_spd(3000, np.random.default_rng(70), pairs_per_row=7.0),
+              32, (-2, -1, 0, 4, 16)),
+             ("poisson2d_32 dup", lambda: w.poisson2d(32), 16, (-1, 0, 4, 16))]
+
+
+@pytest.mark.parametrize("name,make,nb,schedules", DUP_CASES, ids=[c[0] for c in DUP_CASES])
+def test_duplicates_and_unsorted_columns(gpu, orc, name, make, nb, schedules):
+    """Split duplicate entries and shuffled columns go through validation,
+    block extraction and every product schedule (column panels, row-block
+    streaming with 16- or 32-bit columns, lane groups) with oracle parity."""
+    A = split_and_shuffle(make(), 71)
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    key = rows.astype(np.int64) * A.n + A.col_idx
+    assert len(np.unique(key)) < len(key)                       # duplicates present
+    assert np.any(np.diff(A.col_idx)[np.diff(rows) == 0] < 0)   # unsorted rows present
+    M = gpu.precondition(dev(A), block_size=nb)
+    r = w.rhs(A.n, 72)
+    z = gpu.apply(M, torch.as_tensor(r, device=DEV)).cpu().numpy()
+    zo = orc.Precond.uniform(A, nb).apply(r)
+    assert _rel(z, zo) <= 1e-10
+    b = w.rhs(A.n, 73)
+    for lanes in schedules:
+        print(f"case {name} lanes={lanes}", flush=True)
+        _pcg_parity(gpu, orc, A, b, nb, case=name, spmv_lanes=lanes)

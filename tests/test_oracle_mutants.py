@@ -30,6 +30,10 @@ MUTANTS = {
                             "for (int i = 0; i < n; ++i) r[i] -= alpha * p[i];"),
     "pcg_direction_unpreconditioned": ("for (int i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];",
                                        "for (int i = 0; i < n; ++i) p[i] = r[i] + beta * p[i];"),
+    "pcg_never_replaces": ("if (tres <= tol) break;", "break;"),
+    "pcg_replacement_not_counted": ("info->replacements++;", "info->replacements += 0;"),
+    "pcg_replaces_without_iterations_left": ("info->replacements >= max_replacements || k >= max_iter",
+                                             "info->replacements >= max_replacements"),
     "pcg_true_residual_sign": ("for (int i = 0; i < n; ++i) q[i] = b[i] - q[i];\n        double tres",
                                "for (int i = 0; i < n; ++i) q[i] = b[i] + q[i];\n        double tres"),
     # (dropping the beta_{j-1} u_{j-1} term is not listed: with full CGS2

@@ -506,3 +506,70 @@ def test_value_grad_vs_finite_differences(orc):
         Lm = _loss_dense(w.CsrMatrix(30, A.row_ptr, A.col_idx, vm), b, xt)
         fd = (Lp - Lm) / (2 * h)
         assert abs(fd - grad[k]) <= 1e-6 * max(1.0, abs(fd))
+
+
+# ---------------------------------------------------------------- residual replacement
+
+def _true_residual_ld(A, x, b):
+    """||b - A x|| / ||b|| evaluated in extended precision (x86 long double,
+    64-bit mantissa): independent of the oracle's FP64 evaluation and far
+    more accurate than its ~4e-16 rounding floor."""
+    D = A.to_dense().astype(np.longdouble)
+    r = b.astype(np.longdouble) - D @ np.asarray(x).astype(np.longdouble)
+    return float(np.sqrt(np.sum(r * r)) / np.sqrt(np.sum(b.astype(np.longdouble) ** 2)))
+
+
+def test_pcg_residual_replacement_converges(orc):
+    """2D 32x32, blocks of 16, tol 1e-14: the recursive residual drifts from
+    b - A x, so when the recursion first meets tol the true residual does not
+    (Section 3.7's check).  A solve may only report OK with a true residual
+    <= tol; that needs a replacement here, and the reported true residual is
+    the real one (an extended-precision evaluation agrees to the FP64 floor).
+    x equals a dense LAPACK solve."""
+    W = w.workload("poisson2d_32")
+    M = orc.Precond.uniform(W.A, 16)
+    r = orc.pcg(W.A, W.b, M, tol=1e-14, max_replacements=3)
+    assert r.status == "OK" and r.rel_res_true <= 1e-14 and r.replacements >= 1
+    assert abs(_true_residual_ld(W.A, r.x, W.b) - r.rel_res_true) <= 1e-15
+    xs = sl.solve(W.A.to_dense(), W.b, assume_a="pos")
+    assert np.linalg.norm(r.x - xs) / np.linalg.norm(xs) <= 1e-12
+    # without the replacement budget the same recursion ends unconverged
+    r0 = orc.pcg(W.A, W.b, M, tol=1e-14, max_replacements=0)
+    assert r0.status == "ENOCONV" and r0.replacements == 0 and r0.rel_res_true > 1e-14
+    assert abs(_true_residual_ld(W.A, r0.x, W.b) - r0.rel_res_true) <= 1e-15
+
+
+@pytest.mark.parametrize("nb", [16, 0])
+def test_pcg_replacement_budget_below_rounding_floor(orc, nb):
+    """tol 1e-16 lies below the rounding floor of an FP64 evaluation of
+    b - A x (~4e-16 here), so every true-residual check fails: the solve
+    ends ENOCONV after exactly max_replacements restarts, each followed by
+    at least one iteration, and every reported true residual is the real one
+    and above tol."""
+    W = w.workload("poisson2d_32")
+    M = orc.Precond.uniform(W.A, nb) if nb else None
+    prev = 0
+    for m in range(4):
+        r = orc.pcg(W.A, W.b, M, tol=1e-16, max_replacements=m)
+        assert r.status == "ENOCONV" and r.replacements == m and r.iterations < W.A.n
+        assert r.iterations > prev
+        prev = r.iterations
+        t = _true_residual_ld(W.A, r.x, W.b)
+        assert t > 1e-16 and abs(t - r.rel_res_true) <= 1e-15
+
+
+def test_pcg_no_replacement_without_iterations_left(orc):
+    """When the recursion meets tol at exactly max_iter and the true residual
+    does not, no iteration is left for a restart: ENOCONV, the replacement
+    count unchanged and x the last iterate; one more allowed iteration is
+    enough to converge after the replacement."""
+    W = w.workload("poisson2d_32")
+    M = orc.Precond.uniform(W.A, 16)
+    k1 = orc.pcg(W.A, W.b, M, tol=1e-14, max_replacements=0).iterations
+    full = orc.pcg(W.A, W.b, M, tol=1e-14, max_replacements=3)
+    assert full.replacements == 1 and full.iterations == k1 + 1
+    r = orc.pcg(W.A, W.b, M, tol=1e-14, max_iter=k1, max_replacements=3)
+    assert r.status == "ENOCONV" and r.iterations == k1 and r.replacements == 0
+    assert r.rel_res_true > 1e-14
+    r = orc.pcg(W.A, W.b, M, tol=1e-14, max_iter=k1 + 1, max_replacements=3)
+    assert r.status == "OK" and r.iterations == k1 + 1 and r.replacements == 1
