@@ -6,9 +6,16 @@ links or calls anything here, and nothing here calls the GPU library.
 
 Each wrapper takes NumPy arrays and returns NumPy arrays; the arithmetic
 (all of it FP64, sequential sums, no FMA contraction) happens in C.
+
+Two builds of the same source: ``liboracle.so`` (sequential; every parity
+check uses it) and ``liboracle_omp.so`` (OpenMP, used only to time the oracle
+on all host cores: its dot products sum fixed per-thread chunks in thread
+order, so it rounds differently).  Calls go to the sequential build unless
+they run inside ``with timing_threads(k):``.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import dataclasses
 import os
@@ -19,6 +26,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "bjp_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
 # A test that plants a mistake in a copy of the oracle points this at the
 # mutant's build; it is never set by the product or the benchmark.
 _LIB_OVERRIDE = os.environ.get("BJP_ORACLE_LIB")
@@ -29,14 +37,22 @@ _i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
 _f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 
 
+GCC_FLAGS = ["-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-Wall"]
+
+
+def _compile(out: str, extra, force: bool) -> str:
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp"
+        subprocess.check_call(["gcc", *GCC_FLAGS, *extra, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, out)
+    return out
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, no FMA contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math",
-                               "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+    """Compile the oracle with gcc (-O2, no FMA contraction): the sequential
+    build and the OpenMP timing build."""
+    _compile(_LIB_OMP, ["-fopenmp"], force)
+    return _compile(_LIB, ["-Wno-unknown-pragmas"], force)
 
 
 class _PcgInfo(C.Structure):
@@ -44,17 +60,13 @@ class _PcgInfo(C.Structure):
                 ("rel_res_recursive", C.c_double), ("rel_res_true", C.c_double)]
 
 
-_lib = None
+_libs = {}
+_timing = None   # the OpenMP build while inside timing_threads()
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if _LIB_OVERRIDE:
-            L = C.CDLL(_LIB_OVERRIDE)
-        else:
-            build(force=False)
-            L = C.CDLL(_LIB)
+def _load(path: str):
+    if path not in _libs:
+        L = C.CDLL(path)
         L.orc_csr_validate.argtypes = [C.c_int, _i32p, _i32p, _f64p]
         L.orc_spmv.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, _f64p]
         L.orc_dot.argtypes = [C.c_int, _f64p, _f64p]
@@ -79,8 +91,36 @@ def lib():
                                            C.POINTER(C.c_double)]
         L.orc_value_grad.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, _f64p]
         L.orc_edge_grad.argtypes = [C.c_int, _i32p, _i32p, C.c_int, _i32p, _f64p, _f64p, _f64p]
-        _lib = L
-    return _lib
+        L.orc_set_threads.argtypes = [C.c_int]
+        _libs[path] = L
+    return _libs[path]
+
+
+def lib():
+    """The build the next call goes to (sequential unless timing_threads)."""
+    if _timing is not None:
+        return _timing
+    if _LIB_OVERRIDE:
+        return _load(_LIB_OVERRIDE)
+    build(force=False)
+    return _load(_LIB)
+
+
+@contextlib.contextmanager
+def timing_threads(threads: int = 0):
+    """Route the oracle calls inside the block to the OpenMP timing build with
+    `threads` threads (0: OpenMP's default).  Yields the thread count used.
+    For timing only: its dot products round differently from the parity
+    build."""
+    global _timing
+    _compile(_LIB_OMP, ["-fopenmp"], False)
+    L = _load(_LIB_OMP)
+    used = L.orc_set_threads(int(threads))
+    prev, _timing = _timing, L
+    try:
+        yield used
+    finally:
+        _timing = prev
 
 
 def _csr(A):
@@ -155,8 +195,9 @@ class Precond:
         self.offsets = np.ascontiguousarray(offsets, np.int32)
         self.n = n
         st, fb = C.c_int(0), C.c_int(-1)
-        self._h = lib().orc_precondition(n, rp, ci, v, len(self.offsets) - 1, self.offsets,
-                                         C.byref(st), C.byref(fb))
+        self._lib = lib()
+        self._h = self._lib.orc_precondition(n, rp, ci, v, len(self.offsets) - 1, self.offsets,
+                                             C.byref(st), C.byref(fb))
         if not self._h:
             raise OracleError(st.value, fb.value)
 
@@ -177,7 +218,7 @@ class Precond:
 
     def __del__(self):
         if getattr(self, "_h", None):
-            lib().orc_precond_free(self._h)
+            self._lib.orc_precond_free(self._h)
             self._h = None
 
 

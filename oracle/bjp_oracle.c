@@ -9,7 +9,16 @@
  * library.
  *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no FMA contraction, all
- * sums sequential left to right, single thread).
+ * sums sequential left to right, single thread).  This is the build every
+ * parity check uses.
+ *
+ * Timing build (-fopenmp, used only to time the oracle on all host cores):
+ * the loops marked "omp" below run in parallel.  Row products, element-wise
+ * vector updates and block solves give the same values as the sequential
+ * build; a dot product becomes fixed contiguous per-thread chunks (static
+ * split of [0, n) by thread number), each summed left to right, then the
+ * chunk sums added in thread order: deterministic for a given thread count,
+ * but rounded differently from the sequential sum.
  *
  * What it follows (paper: "Optimised Hybrid Classical-Quantum Algorithm ...",
  * arXiv 2410.02408):
@@ -44,6 +53,9 @@
  */
 #include <math.h>
 #include <stdint.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -78,6 +90,7 @@ int orc_csr_validate(int n, const int *row_ptr, const int *col, const double *va
 void orc_spmv(int n, const int *row_ptr, const int *col, const double *val,
               const double *x, double *y)
 {
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < n; ++i) {
         double s = 0.0;
         for (int k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
@@ -88,9 +101,42 @@ void orc_spmv(int n, const int *row_ptr, const int *col, const double *val,
 
 double orc_dot(int n, const double *a, const double *b)
 {
+#ifdef _OPENMP
+    /* timing build only: per-thread chunks, chunk sums in thread order */
+    double part[256];
+    int nt = omp_get_max_threads();
+    if (nt > 256) nt = 256;
+#pragma omp parallel num_threads(nt)
+    {
+        int t = omp_get_thread_num(), used = omp_get_num_threads();
+        long lo = (long)n * t / used, hi = (long)n * (t + 1) / used;
+        double s = 0.0;
+        for (long i = lo; i < hi; ++i) s += a[i] * b[i];
+        part[t] = s;
+#pragma omp single
+        nt = used;
+    }
+    double s = 0.0;
+    for (int t = 0; t < nt; ++t) s += part[t];
+    return s;
+#else
     double s = 0.0;
     for (int i = 0; i < n; ++i) s += a[i] * b[i];
     return s;
+#endif
+}
+
+/* Threads of the timing build (no effect on the sequential build); returns
+ * the number the parallel loops will use. */
+int orc_set_threads(int threads)
+{
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+    return omp_get_max_threads();
+#else
+    (void)threads;
+    return 1;
+#endif
 }
 
 /* ------------------------------------------------------------------ */
@@ -228,6 +274,7 @@ orc_precond *orc_precondition(int n, const int *row_ptr, const int *col, const d
 /* z = M^-1 r, block by block. */
 void orc_apply(const orc_precond *P, const double *r, double *z)
 {
+#pragma omp parallel for schedule(static)
     for (int t = 0; t < P->nblocks; ++t) {
         int s = P->offsets[t], e = P->offsets[t + 1];
         orc_chol_solve(e - s, P->L + P->tile_at[t], r + s, z + s);
@@ -301,6 +348,7 @@ int orc_pcg(int n, const int *row_ptr, const int *col, const double *val,
     for (;;) {
         /* (re)start: r = b - A x, z = M^-1 r, p = z */
         orc_spmv(n, row_ptr, col, val, x, q);
+#pragma omp parallel for schedule(static)
         for (int i = 0; i < n; ++i) r[i] = b[i] - q[i];
         double rr = orc_dot(n, r, r);
         if (!isfinite(rr)) { status = ORC_ENONFINITE; break; }
@@ -317,7 +365,9 @@ int orc_pcg(int n, const int *row_ptr, const int *col, const double *val,
                 double sigma = orc_dot(n, p, q);
                 if (!(sigma > 0.0)) { status = isfinite(sigma) ? ORC_EBREAKDOWN : ORC_ENONFINITE; break; }
                 double alpha = rho / sigma;
+#pragma omp parallel for schedule(static)
                 for (int i = 0; i < n; ++i) x[i] += alpha * p[i];
+#pragma omp parallel for schedule(static)
                 for (int i = 0; i < n; ++i) r[i] -= alpha * q[i];
                 ++k;  /* iterations = completed updates of x */
                 rr = orc_dot(n, r, r);
@@ -329,6 +379,7 @@ int orc_pcg(int n, const int *row_ptr, const int *col, const double *val,
                 double rho_new = orc_dot(n, r, z);
                 if (!(rho_new > 0.0)) { status = isfinite(rho_new) ? ORC_EBREAKDOWN : ORC_ENONFINITE; break; }
                 double beta = rho_new / rho;
+#pragma omp parallel for schedule(static)
                 for (int i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
                 rho = rho_new;
             }
@@ -336,6 +387,7 @@ int orc_pcg(int n, const int *row_ptr, const int *col, const double *val,
         }
         /* true-residual check (Section 3.7) */
         orc_spmv(n, row_ptr, col, val, x, q);
+#pragma omp parallel for schedule(static)
         for (int i = 0; i < n; ++i) q[i] = b[i] - q[i];
         double tres = sqrt(orc_dot(n, q, q)) / bnorm;
         info->rel_res_true = tres;
@@ -395,15 +447,18 @@ int orc_lanczos(int n, const int *row_ptr, const int *col, const double *val,
         orc_spmv(n, row_ptr, col, val, vj, r);            /* w = A v_j */
         double a = orc_dot(n, vj, r);
         alpha[j] = a;
+#pragma omp parallel for schedule(static)
         for (int i = 0; i < n; ++i) r[i] -= a * uj[i];
         if (j > 0) {
             double *up = U + (size_t)(j - 1) * n;
+#pragma omp parallel for schedule(static)
             for (int i = 0; i < n; ++i) r[i] -= beta_prev * up[i];
         }
         for (int pass = 0; pass < 2; ++pass) {              /* CGS2 */
             for (int l = 0; l <= j; ++l) c[l] = orc_dot(n, V + (size_t)l * n, r);
             for (int l = 0; l <= j; ++l) {
                 double *ul = U + (size_t)l * n;
+#pragma omp parallel for schedule(static)
                 for (int i = 0; i < n; ++i) r[i] -= c[l] * ul[i];
             }
         }
@@ -417,6 +472,7 @@ int orc_lanczos(int n, const int *row_ptr, const int *col, const double *val,
         if (bj > scale) scale = bj;
         beta[j] = bj;
         double *un = U + (size_t)(j + 1) * n, *vn = V + (size_t)(j + 1) * n;
+#pragma omp parallel for schedule(static)
         for (int i = 0; i < n; ++i) { un[i] = r[i] / bj; vn[i] = z[i] / bj; }
         beta_prev = bj;
     }
