@@ -199,6 +199,38 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
                   const bjp_pcg_opts_t *opts, void *ws, size_t ws_bytes,
                   bjp_pcg_info_t *info /* host out */, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Allocation-free solve, for callers that cannot allocate device memory or
+ * pass a workspace (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).
+ * ------------------------------------------------------------------------ */
+
+/* Size of the library's static scratch: one copy per GPU, held from the
+ * library's first use on that GPU until the process ends. */
+#define BJP_NOALLOC_SCRATCH_BYTES (128u << 20)
+
+/* bjp_pcg_solve with the library's static scratch as its workspace: same
+ * arguments minus the workspace, same algorithm, kernels and results for the
+ * same options.  Differences:
+ *   - The scratch must hold the solver's vectors: about 40 n + 2 nnz bytes
+ *     plus 67 KB (the bjp_pcg_workspace size without the column-panel copy);
+ *     a larger system returns BJP_EWORKSPACE before any HIP call.  That
+ *     admits up to ~2.48M rows of 7 entries (the 128^3 stencil fits).
+ *   - The iteration's product never uses column panels (spmv_lanes = -2 is
+ *     BJP_EINVAL; the automatic choice takes the CSR schedule).
+ *   - Host polls copy the solver state into ordinary host memory and
+ *     synchronise `stream` (no pinned host memory, no events).
+ * Nothing is allocated: no device memory, no pinned host memory.  The
+ * scratch of the current device is used, so `stream` must belong to the
+ * current device.  Every call on one GPU shares that GPU's scratch, which
+ * keeps the last call's contents (the solver initialises everything it
+ * reads): calls that overlap on one GPU, from several host threads or on
+ * several streams, race and give wrong results.  Synchronises `stream`;
+ * `info` (host) is always filled. */
+int bjp_pcg_solve_noalloc(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, double *x,
+                          const bjp_pcg_opts_t *opts, bjp_pcg_info_t *info /* host out */,
+                          hipStream_t stream);
+
 typedef struct {
     int32_t status;       /* bjp_status                                          */
     int32_t steps_done;   /* Lanczos steps taken (< steps after an invariant-

@@ -110,6 +110,7 @@ def load():
     L.bjp_apply.argtypes = [P(PrecondT), vp, vp, vp]
     L.bjp_pcg_workspace.argtypes = [P(CsrT), P(sz)]
     L.bjp_pcg_solve.argtypes = [P(CsrT), P(PrecondT), vp, vp, P(PcgOptsT), vp, sz, P(PcgInfoT), vp]
+    L.bjp_pcg_solve_noalloc.argtypes = [P(CsrT), P(PrecondT), vp, vp, P(PcgOptsT), P(PcgInfoT), vp]
     L.bjp_kappa_workspace.argtypes = [P(CsrT), C.c_int, P(sz)]
     L.bjp_kappa_estimate.argtypes = [P(CsrT), P(PrecondT), vp, C.c_int, vp, vp, vp, sz,
                                      P(KappaInfoT), vp]
@@ -319,6 +320,31 @@ def pcg_solve(A: DeviceCsr, M: Precond | None, b, tol: float = 1e-10, max_iter: 
         raise BjpError(st, "bjp_pcg_solve")
     return x, PcgInfo(STATUS[info.status], info.iterations, info.replacements, info.polls,
                       info.rel_res_recursive, info.rel_res_true)
+
+
+NOALLOC_SCRATCH_BYTES = 128 << 20
+
+
+def pcg_solve_noalloc(A: DeviceCsr, M: Precond | None, b: torch.Tensor, x: torch.Tensor,
+                      tol: float = 1e-10, max_iter: int | None = None, x0_given: bool = False,
+                      max_replacements: int = 3, check_every: int = 0, spmv_lanes: int = 0,
+                      history: torch.Tensor | None = None):
+    """bjp_pcg_solve_noalloc: the solve on the library's static scratch.  b and
+    x are caller-owned device tensors of n float64 (x holds x0 when
+    x0_given); nothing is allocated here or in the library.  Returns
+    PcgInfo; argument/size/runtime errors raise BjpError."""
+    L = load()
+    A = as_csr(A)
+    opts = PcgOptsT(tol, int(max_iter or 0), 1 if x0_given else 0,
+                    -1 if max_replacements == 0 else int(max_replacements), int(check_every),
+                    int(spmv_lanes), 0, history.data_ptr() if history is not None else None, None)
+    info = PcgInfoT()
+    st = L.bjp_pcg_solve_noalloc(C.byref(A.struct()), C.byref(M.handle) if M is not None else None,
+                                 _ptr(b), _ptr(x), C.byref(opts), C.byref(info), _stream(A.device))
+    if st in (-1, -6, -7):
+        raise BjpError(st, "bjp_pcg_solve_noalloc")
+    return PcgInfo(STATUS[info.status], info.iterations, info.replacements, info.polls,
+                   info.rel_res_recursive, info.rel_res_true)
 
 
 @dataclasses.dataclass

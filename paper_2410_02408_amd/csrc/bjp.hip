@@ -8,6 +8,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "adjoint.hpp"
@@ -663,6 +664,10 @@ int bjp_apply(const bjp_precond_t *M, const double *r, double *z, hipStream_t st
     return BJP_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
 // Column panels (see spmv.hpp) need rows of at least kPanelMeanRow entries
 // on average; they are chosen automatically once the gathered vector is
 // larger than an XCD's L2 could hold (n >= 2^20 rows, 8 MB), or forced with
@@ -691,19 +696,39 @@ size_t delta16_bytes(const bjp_csr_t *A) {
     return short_rows(A) ? al256(sizeof(int16_t) * (size_t)std::max(A->nnz, 1)) + al256(64) : 0;
 }
 
+// PCG workspace: five vectors, two sets of reduction partials, two states,
+// flags, zeros, the 16-bit column offsets (short rows) and, when allowed,
+// the column-panel copy (long rows).
+size_t pcg_ws_bytes(const bjp_csr_t *A, bool with_panels) {
+    const size_t vec = al256(sizeof(double) * (size_t)std::max(A->n, 1));
+    return 5 * vec + 2 * al256(sizeof(double) * 2 * kMaxRedWG) + 2 * al256(sizeof(PcgState)) + 2 * al256(64) +
+           (with_panels ? panel_bytes(A) : 0) + delta16_bytes(A);
+}
+
+}  // namespace
+
+extern "C" {
+
 int bjp_pcg_workspace(const bjp_csr_t *A, size_t *bytes) {
     if (!bytes) return BJP_EINVAL;
     *bytes = 0;
     if (check_csr_host(A) != BJP_OK) return BJP_EINVAL;
-    const size_t vec = al256(sizeof(double) * (size_t)std::max(A->n, 1));
-    *bytes = 5 * vec + 2 * al256(sizeof(double) * 2 * kMaxRedWG) + 2 * al256(sizeof(PcgState)) + 2 * al256(64) +
-             panel_bytes(A) + delta16_bytes(A);
+    *bytes = pcg_ws_bytes(A, true);
     return BJP_OK;
 }
 
-int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, double *x,
-                  const bjp_pcg_opts_t *opts, void *ws, size_t ws_bytes, bjp_pcg_info_t *info,
-                  hipStream_t stream) {
+}  // extern "C"
+
+namespace {
+
+// The solver behind bjp_pcg_solve and bjp_pcg_solve_noalloc.  no_alloc: the
+// workspace is the library's static scratch and nothing may be allocated, so
+// the iteration's product never takes the column panels (their copy of A is
+// not part of the scratch) and the host polls read the state into ordinary
+// host memory with a stream synchronisation (no pinned slots, no events).
+int pcg_solve_impl(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, double *x,
+                   const bjp_pcg_opts_t *opts, void *ws, size_t ws_bytes, bjp_pcg_info_t *info,
+                   hipStream_t stream, bool no_alloc) {
     if (!info) return BJP_EINVAL;
     std::memset(info, 0, sizeof(*info));
     auto fail = [&](int st) {
@@ -721,8 +746,8 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
     if (o.max_replacements == 0) o.max_replacements = 3;
     else if (o.max_replacements < 0) o.max_replacements = 0;
     if (o.check_every <= 0) o.check_every = 16;
-    size_t need = 0;
-    bjp_pcg_workspace(A, &need);
+    if (no_alloc && o.spmv_lanes == -2) return fail(BJP_EINVAL);
+    const size_t need = pcg_ws_bytes(A, !no_alloc);
     if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255)) return fail(BJP_EWORKSPACE);
     if (n == 0) return fail(BJP_OK);
 
@@ -748,7 +773,7 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
 
     // the iteration's product q = A p: column panels or the CSR schedule;
     // the residual products always take the CSR schedule
-    const bool panels = use_panels(o.spmv_lanes, A);
+    const bool panels = !no_alloc && use_panels(o.spmv_lanes, A);
     if (o.spmv_lanes == -2 && !panels) return fail(BJP_EINVAL);
     const int gs = spmv_schedule(o.spmv_lanes == -2 ? 0 : o.spmv_lanes, A);
     const RowLaunch Ls = spmv_shape(n, gs);
@@ -943,20 +968,27 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
     // state copied after the previous batch is examined, so the GPU does not
     // wait for the host.  Iterations launched after convergence return at
     // once.  Batch sizes follow the observed convergence rate.
-    PcgState *hs = pinned_states();
+    // Without allocation the slots are ordinary host memory and a poll waits
+    // for the whole stream: the launches of the next batch are already
+    // queued, so the GPU still runs ahead of the host by one batch.
+    PcgState local_slots[2];
+    PcgState *hs = no_alloc ? local_slots : pinned_states();
     if (!hs) return fail(BJP_EHIP);
     EventPair ev;
-    HIP_TRY(hipEventCreateWithFlags(&ev.e[0], hipEventDisableTiming));
-    HIP_TRY(hipEventCreateWithFlags(&ev.e[1], hipEventDisableTiming));
+    if (!no_alloc) {
+        HIP_TRY(hipEventCreateWithFlags(&ev.e[0], hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&ev.e[1], hipEventDisableTiming));
+    }
     auto post = [&](int slot) -> int {
         commit();
         HIP_TRY(hipMemcpyAsync(&hs[slot], st, sizeof(PcgState), hipMemcpyDeviceToHost, stream));
-        HIP_TRY(hipEventRecord(ev.e[slot], stream));
+        if (!no_alloc) HIP_TRY(hipEventRecord(ev.e[slot], stream));
         return BJP_OK;
     };
     auto take = [&](int slot, PcgState &out) -> int {
         HIP_TRY(hipGetLastError());
-        HIP_TRY(hipEventSynchronize(ev.e[slot]));
+        if (no_alloc) HIP_TRY(hipStreamSynchronize(stream));
+        else HIP_TRY(hipEventSynchronize(ev.e[slot]));
         out = hs[slot];
         return BJP_OK;
     };
@@ -1025,6 +1057,55 @@ int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, d
     info->rel_res_recursive = h.relres;
     info->rel_res_true = h.relres_true;
     return status;
+}
+
+// ---------------------------------------------------------------------------
+// Static scratch of the allocation-free solver: one copy per GPU, held from
+// the library's first use on that GPU until the process ends.  Host code
+// never uses the symbol itself as an address: each device's copy is looked
+// up once with hipGetSymbolAddress (with that device current) and the
+// pointer kept.
+// ---------------------------------------------------------------------------
+__device__ __align__(256) unsigned char scratch[BJP_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mutex;
+void *scratch_ptrs[kMaxDevices] = {};
+
+// This device's copy of `scratch` (nullptr if the lookup fails).
+void *device_scratch() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    if (!scratch_ptrs[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        scratch_ptrs[dev] = p;
+    }
+    return scratch_ptrs[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, double *x,
+                  const bjp_pcg_opts_t *opts, void *ws, size_t ws_bytes, bjp_pcg_info_t *info,
+                  hipStream_t stream) {
+    return pcg_solve_impl(A, M, b, x, opts, ws, ws_bytes, info, stream, false);
+}
+
+int bjp_pcg_solve_noalloc(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, double *x,
+                          const bjp_pcg_opts_t *opts, bjp_pcg_info_t *info, hipStream_t stream) {
+    if (!info) return BJP_EINVAL;
+    std::memset(info, 0, sizeof(*info));
+    if (check_csr_host(A) != BJP_OK) return info->status = BJP_EINVAL;
+    // sizes first: a system beyond the scratch is refused before any HIP call
+    const size_t need = pcg_ws_bytes(A, false);
+    if (need > (size_t)BJP_NOALLOC_SCRATCH_BYTES) return info->status = BJP_EWORKSPACE;
+    void *ws = device_scratch();
+    if (!ws) return info->status = BJP_EHIP;
+    return pcg_solve_impl(A, M, b, x, opts, ws, BJP_NOALLOC_SCRATCH_BYTES, info, stream, true);
 }
 
 int bjp_kappa_workspace(const bjp_csr_t *A, int steps, size_t *bytes) {
