@@ -779,7 +779,7 @@ int pcg_solve_impl(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, 
     const RowLaunch Ls = spmv_shape(n, gs);
     PanelArgs pa{};
     const RowLaunch Lf = rows_shape(n);
-    const int panel_grid = kPanels * std::min(ceil_div(n, kPanelRowsWG), 8 * device_cus() / kPanels * 4);
+    const int panel_grid = kPanels * std::min(ceil_div(n, kPanelChunk), 8 * device_cus() / kPanels * 4);
     if (panels) {
         pa.n = n;
         pa.nnz = A->nnz;

@@ -408,12 +408,11 @@ __global__ __launch_bounds__(kWG) void k_col_delta16(const int32_t *rp, const in
 // the vector) and a chunk of rows, and writes per-panel partial sums;
 // a second launch adds the kPanels partial sums of each row in panel order
 // and finishes the row as the plain product does.  Measured with random
-// columns over a 32 MB vector (4M rows, 143M entries): 2.75 ms for the plain
-// product, 1.62 ms with 8 panels (16 panels: 2.0 ms).
+// columns over a 32 MB vector (4M rows, 143M entries) and a group of lanes
+// per row: 2.75 ms for the plain product, 1.62 ms with 8 panels (16 panels:
+// 2.0 ms).
 // ---------------------------------------------------------------------------
 constexpr int kPanels = 8;
-constexpr int kPanelLanes = 8;       // lanes per row within a panel
-constexpr int kPanelRowsWG = 256;    // rows per workgroup of the panel product
 constexpr int kScanRows = 2048;      // rows per workgroup of the offset scan (8 per thread)
 
 struct PanelArgs {
@@ -577,27 +576,71 @@ __global__ __launch_bounds__(kWG) void k_panel_scatter(PanelArgs a) {
     }
 }
 
-// Y[q][i] = sum over row i's entries in panel q (of the mode's gathered vector).
+// Y[q][i] = sum over row i's entries in panel q (of the mode's gathered
+// vector), in their order.  Workgroup b takes panel b mod kPanels and chunks
+// of kPanelChunk rows of it; a chunk's entries of the panel are contiguous in
+// the copy (about 4 per row on the power-law family, hundreds for hub rows)
+// and are streamed as in the row-block product: thread t loads entries t,
+// t + 256, ... of a stage (kPanelPer per thread, all issued before the
+// gathers, so each thread keeps kPanelPer gathers in flight and every lane
+// has work), stages the products in LDS, and then adds the products of its
+// kPanelRows rows (t, t + 256, ...) in order.  Measured on the power-law
+// workload (4M rows, 134M entries): 1.55 ms per product with a group of 8
+// lanes per row, 1.05 ms streaming 4 entries per thread over 256-row chunks,
+// 1.02 ms with 8 entries per thread over 512-row chunks (8 over 256 rows:
+// 1.11 ms, half the loads past the chunk's end; gathers that bypass the L1
+// through buffer loads at device scope: 1.08 ms).
+constexpr int kPanelPer = 8;
+constexpr int kPanelRows = 2;
+constexpr int kPanelChunk = kPanelRows * kWG;
 template <int MODE>
 __global__ __launch_bounds__(kWG) void k_spmv_panels(SpmvArgs s, PanelArgs a) {
     int it = 0;
     if (!spmv_state<MODE>(s, it)) return;
     const SpmvMode_<MODE> m(s, it);
+    constexpr int CAP = kPanelPer * kWG;
+    __shared__ double prod[CAP];
     const int q = blockIdx.x % kPanels;
-    const int32_t *prp = a.prp + (size_t)q * (a.n + 1);
-    const int sub = threadIdx.x % kPanelLanes;
-    const int nchunks = (a.n + kPanelRowsWG - 1) / kPanelRowsWG, cstride = gridDim.x / kPanels;
+    const int32_t *__restrict__ prp = a.prp + (size_t)q * (a.n + 1);
+    const int tid = threadIdx.x;
+    const int nchunks = (a.n + kPanelChunk - 1) / kPanelChunk, cstride = gridDim.x / kPanels;
     for (int c = blockIdx.x / kPanels; c < nchunks; c += cstride) {
-        const int r0 = c * kPanelRowsWG, r1 = min(r0 + kPanelRowsWG, a.n);
-        // the kPanelLanes lanes of a row share its trip count (the shuffles below)
-        for (int row = r0 + threadIdx.x / kPanelLanes; row < r1; row += kWG / kPanelLanes) {
-            double acc = 0.0;
-            const int ke = min(prp[row + 1], a.nnz);
-            for (int k = prp[row] + sub; k < ke; k += kPanelLanes)
-                acc += __builtin_nontemporal_load(a.pval + k) * m.gather(__builtin_nontemporal_load(a.pci + k));
+        const int b0 = c * kPanelChunk, b1 = min(b0 + kPanelChunk, a.n);
+        int kb[kPanelRows], ke[kPanelRows];
+        double acc[kPanelRows];
 #pragma unroll
-            for (int off = kPanelLanes / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-            if (sub == 0) __builtin_nontemporal_store(acc, a.Y + (size_t)q * a.n + row);
+        for (int u = 0; u < kPanelRows; ++u) {
+            const int ic = min(b0 + u * kWG + tid, b1 - 1);
+            kb[u] = prp[ic];
+            ke[u] = prp[ic + 1];
+            acc[u] = 0.0;
+        }
+        const int base = prp[b0], end = min(prp[b1], a.nnz);
+        for (int c0 = base; c0 < end; c0 += CAP) {
+            const int c1 = min(c0 + CAP, end);
+            int col[kPanelPer];
+            double vv[kPanelPer];
+#pragma unroll
+            for (int j = 0; j < kPanelPer; ++j) {
+                const int k = c0 + j * kWG + tid;
+                const int kc = k < c1 ? k : c0;
+                col[j] = __builtin_nontemporal_load(a.pci + kc);
+                vv[j] = __builtin_nontemporal_load(a.pval + kc);
+            }
+#pragma unroll
+            for (int j = 0; j < kPanelPer; ++j) prod[j * kWG + tid] = vv[j] * m.gather(col[j]);
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < kPanelRows; ++u) {
+                const int lo = max(kb[u], c0), hi = min(ke[u], c1);
+                for (int k = lo; k < hi; ++k) acc[u] += prod[k - c0];
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int u = 0; u < kPanelRows; ++u) {
+            const int i = b0 + u * kWG + tid;
+            if (i < b1) __builtin_nontemporal_store(acc[u], a.Y + (size_t)q * a.n + i);
         }
     }
 }
