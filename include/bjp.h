@@ -291,6 +291,11 @@ typedef struct {
     int32_t eager;               /* 0: the check_every iterations between polls are
                                     captured once into a hipGraph and replayed;
                                     1: every kernel is launched from the host       */
+    const int32_t *sys_lanes;    /* host [num_systems] or NULL: per-system product
+                                    schedule (as `lanes`; 0 = the batch's `lanes`).
+                                    Systems sharing a schedule share a launch.     */
+    const int32_t *sys_tile_rows;/* host [num_systems] or NULL: per-system rows per
+                                    product tile (as `tile_rows`; 0 = the batch's)  */
 } bjp_batch_opts_t;
 
 /* Per-system result (same layout as the device record the solver writes). */

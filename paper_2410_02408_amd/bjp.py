@@ -417,7 +417,7 @@ class BatchPrecondT(C.Structure):
 class BatchOptsT(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("max_replacements", C.c_int32),
                 ("lanes", C.c_int32), ("tile_rows", C.c_int32), ("check_every", C.c_int32),
-                ("eager", C.c_int32)]
+                ("eager", C.c_int32), ("sys_lanes", C.c_void_p), ("sys_tile_rows", C.c_void_p)]
 
 
 class SystemInfoT(C.Structure):
@@ -483,6 +483,28 @@ class Batch:
     def struct(self) -> BatchT:
         return BatchT(self.num_systems, self.sys_rows.ctypes.data, self.block_sizes.ctypes.data)
 
+    def subset(self, systems, b: torch.Tensor | None = None):
+        """A batch of the listed systems (copied on the device, in the given
+        order) and, if b is given, the matching slices of b."""
+        dev = self.A.device
+        sr = self.sys_rows.astype(np.int64)
+        ep = self.A.row_ptr[torch.as_tensor(sr, device=dev)].cpu().numpy().astype(np.int64)
+        rps, cis, vals, bs, rows = [], [], [], [], [0]
+        nnz0 = 0
+        for s in systems:
+            r0, r1, e0, e1 = sr[s], sr[s + 1], ep[s], ep[s + 1]
+            rps.append(self.A.row_ptr[r0:r1].to(torch.int64) - int(e0) + nnz0)
+            cis.append(self.A.col_idx[e0:e1] - int(r0 - rows[-1]))
+            vals.append(self.A.val[e0:e1])
+            if b is not None:
+                bs.append(b[r0:r1])
+            nnz0 += int(e1 - e0)
+            rows.append(rows[-1] + int(r1 - r0))
+        rps.append(torch.tensor([nnz0], dtype=torch.int64, device=dev))
+        A = DeviceCsr(rows[-1], torch.cat(rps).to(torch.int32), torch.cat(cis), torch.cat(vals))
+        sub = Batch(A, np.asarray(rows, dtype=np.int32), self.block_sizes[np.asarray(systems)])
+        return sub, (torch.cat(bs) if b is not None else None)
+
 
 class BatchPrecond:
     def __init__(self, handle: BatchPrecondT, ws: torch.Tensor):
@@ -522,10 +544,11 @@ class BatchInfo:
 def batch_pcg_solve(B: Batch, M: BatchPrecond, b, tol: float = 1e-10, max_iter: int = 0,
                     lanes: int = 0, tile_rows: int = 0, check_every: int = 0,
                     out: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
-                    graph: bool = True):
+                    graph: bool = True, sys_lanes=None, sys_tile_rows=None):
     """bjp_batch_pcg_solve: every system advances in the same launches (the
     iterations between polls replayed from a captured hipGraph unless
-    graph=False)."""
+    graph=False).  sys_lanes / sys_tile_rows (one int per system, 0 = the
+    batch-wide value) set each system's product schedule."""
     L = _load_batch(load())
     dev = B.A.device
     b = _vec(b, dev)
@@ -537,7 +560,13 @@ def batch_pcg_solve(B: Batch, M: BatchPrecond, b, tol: float = 1e-10, max_iter: 
         if st:
             raise BjpError(st, "bjp_batch_pcg_workspace")
         workspace = _workspace(n.value, dev)
-    opts = BatchOptsT(tol, int(max_iter), 0, int(lanes), int(tile_rows), int(check_every), 0 if graph else 1)
+    sl = None if sys_lanes is None else np.ascontiguousarray(sys_lanes, dtype=np.int32)
+    st_ = None if sys_tile_rows is None else np.ascontiguousarray(sys_tile_rows, dtype=np.int32)
+    for arr in (sl, st_):
+        if arr is not None and len(arr) != B.num_systems:
+            raise ValueError("per-system schedule arrays need one entry per system")
+    opts = BatchOptsT(tol, int(max_iter), 0, int(lanes), int(tile_rows), int(check_every), 0 if graph else 1,
+                      sl.ctypes.data if sl is not None else None, st_.ctypes.data if st_ is not None else None)
     info = BatchInfoT()
     per = (SystemInfoT * B.num_systems)()
     st = L.bjp_batch_pcg_solve(C.byref(csr), C.byref(bs), C.byref(M.handle), _ptr(b), _ptr(x),

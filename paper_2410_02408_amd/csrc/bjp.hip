@@ -457,24 +457,42 @@ size_t batch_precond_bytes(const BatchPlan &P, int precision) {
 constexpr int kPacketsPerTile = 64;
 
 struct BatchTables {
-    std::vector<Tile> rt, pt;               // row tiles, packet tiles (grouped by G)
+    std::vector<Tile> rt, pt;               // row tiles (grouped by SpMV schedule), packet tiles (by G)
     std::vector<int> rt_begin, rt_end;      // per system
     std::vector<int> pt_begin, pt_end;      // per system
+    std::vector<int> rs_gs, rs_begin, rs_end;    // row-tile range of each SpMV schedule
     std::vector<int> cls_g, cls_begin, cls_end;  // packet-tile range of each width G
 };
 
-void make_batch_tables(const BatchPlan &P, int tile_rows, BatchTables &T) {
+// Row tiles of sys_tile_rows[s] rows per system, grouped by the system's SpMV
+// schedule sys_gs[s] (one product launch per schedule present; a system's
+// tiles stay contiguous); packet tiles grouped by lane-group width.
+void make_batch_tables(const BatchPlan &P, const std::vector<int> &sys_tile_rows, const std::vector<int> &sys_gs,
+                       BatchTables &T) {
     const int S = (int)P.sys.size();
     T.rt_begin.assign(S, 0);
     T.rt_end.assign(S, 0);
     T.pt_begin.assign(S, 0);
     T.pt_end.assign(S, 0);
-    for (int s = 0; s < S; ++s) {
-        const SysInfo &si = P.sys[s];
-        T.rt_begin[s] = (int)T.rt.size();
-        for (int r = si.row0; r < si.row0 + si.n; r += tile_rows)
-            T.rt.push_back(Tile{s, r, std::min(r + tile_rows, si.row0 + si.n), 0});
-        T.rt_end[s] = (int)T.rt.size();
+    std::vector<int> kinds(sys_gs);
+    std::sort(kinds.begin(), kinds.end());
+    kinds.erase(std::unique(kinds.begin(), kinds.end()), kinds.end());
+    for (const int g : kinds) {
+        const int b = (int)T.rt.size();
+        for (int s = 0; s < S; ++s) {
+            if (sys_gs[s] != g) continue;
+            const SysInfo &si = P.sys[s];
+            const int tr = sys_tile_rows[s];
+            T.rt_begin[s] = (int)T.rt.size();
+            for (int r = si.row0; r < si.row0 + si.n; r += tr)
+                T.rt.push_back(Tile{s, r, std::min(r + tr, si.row0 + si.n), 0});
+            T.rt_end[s] = (int)T.rt.size();
+        }
+        if ((int)T.rt.size() > b) {
+            T.rs_gs.push_back(g);
+            T.rs_begin.push_back(b);
+            T.rs_end.push_back((int)T.rt.size());
+        }
     }
     for (int G = 1; G <= 64; G <<= 1) {
         const int b = (int)T.pt.size();
@@ -1377,11 +1395,19 @@ int bjp_batch_pcg_solve(const bjp_csr_t *A, const bjp_batch_t *B, const bjp_batc
     if (o.max_replacements == 0) o.max_replacements = 3;
     else if (o.max_replacements < 0) o.max_replacements = 0;
     if (o.check_every <= 0) o.check_every = 16;
-    const int tile_rows = o.tile_rows > 0 ? std::max(256, o.tile_rows) : 2048;
-    const int gs = spmv_schedule(o.lanes, A);
+    // per-system product schedule and tile rows (the batch-wide values where
+    // the per-system arrays are absent or hold 0)
+    std::vector<int> sys_gs(S), sys_tr(S);
+    for (int s = 0; s < S; ++s) {
+        const int ln = o.sys_lanes && o.sys_lanes[s] != 0 ? o.sys_lanes[s] : o.lanes;
+        const int gs = spmv_schedule(ln, A);
+        sys_gs[s] = gs == kStream7 ? 0 : gs;     // one streaming kernel serves both stage sizes
+        const int tr = o.sys_tile_rows && o.sys_tile_rows[s] > 0 ? o.sys_tile_rows[s] : o.tile_rows;
+        sys_tr[s] = tr > 0 ? std::max(256, tr) : 2048;
+    }
 
     BatchTables T;
-    make_batch_tables(P, tile_rows, T);
+    make_batch_tables(P, sys_tr, sys_gs, T);
     const int nrt = (int)T.rt.size(), npt = (int)T.pt.size();
     const int nred = round8(std::max(nrt, npt));
     std::vector<int> caps(S);
@@ -1460,13 +1486,21 @@ int bjp_batch_pcg_solve(const bjp_csr_t *A, const bjp_batch_t *B, const bjp_batc
             else launch_apply_tiles_t<double, MODE>(T.cls_g[c], grid, aa, span, ls);
         }
     };
+    // the product over every row tile: one launch per schedule present
+    auto spmv_all = [&](auto mode_tag, hipStream_t sl) {
+        constexpr int MODE = decltype(mode_tag)::value;
+        for (size_t c = 0; c < T.rs_gs.size(); ++c) {
+            const TileSpan span{tiles, T.rs_begin[c], T.rs_end[c], nrt, static_cast<const SysInfo *>(M->systems)};
+            launch_spmv_tiles<MODE>(T.rs_gs[c], round8(T.rs_end[c] - T.rs_begin[c]), sa, span, sl);
+        }
+    };
     auto start_direction = [&]() {
         apply_all(std::integral_constant<int, APPLY_INIT>{});
         hipLaunchKernelGGL(k_finish_sys<FIN_PCG_START>, dim3(S), dim3(kWG), 0, ls, fa, ptb, pte, npt);
     };
     auto iteration = [&]() {
         hipLaunchKernelGGL(k_direction_tiles, dim3(rgrid), dim3(kWG), 0, ls, states, z, p0, p1, rows);
-        launch_spmv_tiles<SPMV_SIGMA>(gs, rgrid, sa, rows, ls);
+        spmv_all(std::integral_constant<int, SPMV_SIGMA>{}, ls);
         hipLaunchKernelGGL(k_finish_sys<FIN_SIGMA>, dim3(S), dim3(kWG), 0, ls, fa, rtb, rte, nrt);
         apply_all(std::integral_constant<int, APPLY_UPDATE>{});
         hipLaunchKernelGGL(k_finish_sys<FIN_PCG_UPDATE>, dim3(S), dim3(kWG), 0, ls, fa, ptb, pte, npt);
@@ -1506,7 +1540,7 @@ int bjp_batch_pcg_solve(const bjp_csr_t *A, const bjp_batch_t *B, const bjp_batc
     };
 
     sa.resid_phase = 0;
-    launch_spmv_tiles<SPMV_RESID>(gs, rgrid, sa, rows, stream);
+    spmv_all(std::integral_constant<int, SPMV_RESID>{}, stream);
     hipLaunchKernelGGL(k_finish_sys<FIN_RESID_START>, dim3(S), dim3(kWG), 0, stream, fa, rtb, rte, nrt);
     start_direction();
 
@@ -1522,7 +1556,7 @@ int bjp_batch_pcg_solve(const bjp_csr_t *A, const bjp_batch_t *B, const bjp_batc
         }
         // true residual of every system; re-open the ones above tol
         sa.resid_phase = 1;
-        launch_spmv_tiles<SPMV_RESID>(gs, rgrid, sa, rows, stream);
+        spmv_all(std::integral_constant<int, SPMV_RESID>{}, stream);
         hipLaunchKernelGGL(k_finish_sys<FIN_RESID_TRUE>, dim3(S), dim3(kWG), 0, stream, fa, rtb, rte, nrt);
         sa.resid_phase = 0;
         if ((st = read_states()) != BJP_OK) return fail(st);
