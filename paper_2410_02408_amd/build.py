@@ -1,4 +1,5 @@
-"""Build libbjp.so (the HIP library) in-tree for gfx950.
+"""Build libbjp.so (the HIP library) in-tree for gfx950, and
+libbjp_calib.so (the benchmark's bandwidth references, calib/calib.hip).
 
     python -m paper_2410_02408_amd.build
 """
@@ -12,6 +13,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 SRC = os.path.join(PKG, "csrc", "bjp.hip")
 LIB = os.path.join(PKG, "libbjp.so")
+CALIB_SRC = os.path.join(PKG, "calib", "calib.hip")
+CALIB_LIB = os.path.join(PKG, "libbjp_calib.so")
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -43,18 +46,23 @@ def hipcc() -> str:
     return cand if os.path.exists(cand) else "hipcc"
 
 
-def build(verbose: bool = False) -> str:
-    """Compile the library (always recompiles)."""
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-o", tmp, SRC]
-    res = subprocess.run(cmd, capture_output=True, text=True)
+def _hipcc(src: str, out: str, verbose: bool) -> str:
+    tmp = out + ".tmp"
+    res = subprocess.run([hipcc(), *HIPCC_FLAGS, "-o", tmp, src], capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libbjp.so")
+        raise RuntimeError(f"hipcc failed building {os.path.basename(out)}")
     if verbose:
         sys.stdout.write(res.stdout)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the library and the benchmark's calibration kernels (always
+    recompiles)."""
+    _hipcc(CALIB_SRC, CALIB_LIB, verbose)
+    return _hipcc(SRC, LIB, verbose)
 
 
 if __name__ == "__main__":
