@@ -18,6 +18,7 @@
 #include "common.hpp"
 #include "finish.hpp"
 #include "lanczos.hpp"
+#include "small.hpp"
 #include "spmv.hpp"
 
 using namespace bjp;
@@ -261,6 +262,25 @@ template <int MODE>
 void launch_apply(const bjp_precond_t *M, int grid, const ApplyArgs &a, hipStream_t s) {
     if (M->precision == BJP_FP32_STORE) launch_apply_t<float, MODE>(M->group, grid, a, s);
     else launch_apply_t<double, MODE>(M->group, grid, a, s);
+}
+
+template <typename TS>
+void launch_small_t(int G, const SmallArgs &a, hipStream_t s) {
+    switch (G) {
+        case 1: hipLaunchKernelGGL((k_pcg_small<1, TS, true>), dim3(1), dim3(kSmallWG), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_pcg_small<2, TS, true>), dim3(1), dim3(kSmallWG), 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_pcg_small<4, TS, true>), dim3(1), dim3(kSmallWG), 0, s, a); break;
+        case 8: hipLaunchKernelGGL((k_pcg_small<8, TS, true>), dim3(1), dim3(kSmallWG), 0, s, a); break;
+        case 16: hipLaunchKernelGGL((k_pcg_small<16, TS, true>), dim3(1), dim3(kSmallWG), 0, s, a); break;
+        case 32: hipLaunchKernelGGL((k_pcg_small<32, TS, true>), dim3(1), dim3(kSmallWG), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_pcg_small<64, TS, true>), dim3(1), dim3(kSmallWG), 0, s, a); break;
+    }
+}
+
+void launch_small(const bjp_precond_t *M, const SmallArgs &a, hipStream_t s) {
+    if (!M) hipLaunchKernelGGL((k_pcg_small<1, double, false>), dim3(1), dim3(kSmallWG), 0, s, a);
+    else if (M->precision == BJP_FP32_STORE) launch_small_t<float>(M->group, a, s);
+    else launch_small_t<double>(M->group, a, s);
 }
 
 // gs = lanes per row of the lane-group schedule; 0 = row-block streaming with
@@ -788,6 +808,51 @@ int pcg_solve_impl(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, 
 
     int s = run_validate(A, flags, stream);
     if (s != BJP_OK) return fail(s);
+
+    // Small systems (automatic product schedule, no kernel timing): the whole
+    // solve in one workgroup (small.hpp), the same algorithm and decisions.
+    if (n <= kSmallMaxRows && (long long)A->nnz <= (long long)kSmallMaxMeanRow * n && o.spmv_lanes == 0 &&
+        !o.timing) {
+        SmallArgs sm{};
+        sm.n = n;
+        sm.rp = A->row_ptr;
+        sm.ci = A->col_idx;
+        sm.val = A->val;
+        sm.b = b;
+        sm.x = x;
+        sm.r = r;
+        sm.z = z;
+        sm.p = p0;
+        sm.q = q;
+        if (M) {
+            sm.nblocks = M->num_blocks;
+            sm.num_packets = M->num_packets;
+            sm.uniform_nb = M->block_size;
+            sm.off = M->offsets;
+            sm.tiles = M->tiles;
+        }
+        sm.tol = o.tol;
+        sm.max_iter = o.max_iter;
+        sm.max_repl = o.max_replacements;
+        sm.x0_given = o.x0_given;
+        sm.hist = o.history;
+        sm.out = st;
+        sm.repl_out = flags + 8;
+        launch_small(M, sm, stream);
+        HIP_TRY(hipGetLastError());
+        PcgState h{};
+        int32_t rep = 0;
+        HIP_TRY(hipMemcpyAsync(&h, st, sizeof(PcgState), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipMemcpyAsync(&rep, flags + 8, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        info->status = h.status;
+        info->iterations = h.it;
+        info->replacements = rep;
+        info->polls = 1;
+        info->rel_res_recursive = h.relres;
+        info->rel_res_true = h.relres_true;
+        return h.status;
+    }
 
     // the iteration's product q = A p: column panels or the CSR schedule;
     // the residual products always take the CSR schedule

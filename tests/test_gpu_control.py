@@ -22,8 +22,13 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
+# spmv_lanes = 0: the one-workgroup solver (1024 rows); -1: the multi-launch solver
+BOTH_SOLVERS = pytest.mark.parametrize("lanes", [0, -1], ids=["one-workgroup", "multi-launch"])
+
+
+@BOTH_SOLVERS
 @pytest.mark.parametrize("nb", [16, 0])
-def test_replacement_budget_matches_oracle(gpu, orc, nb):
+def test_replacement_budget_matches_oracle(gpu, orc, nb, lanes):
     """tol 1e-16 (below the rounding floor of b - A x): every true-residual
     check fails, so both sides end ENOCONV after exactly max_replacements
     restarts.  Runs with budgets 0..3 give the length of every leg between
@@ -36,7 +41,7 @@ def test_replacement_budget_matches_oracle(gpu, orc, nb):
     prev_g = prev_o = 0
     for m in range(4):
         print(f"case nb={nb} max_replacements={m}", flush=True)
-        x, info = gpu.pcg_solve(A, Md, W.b, tol=1e-16, max_replacements=m if m else 0)
+        x, info = gpu.pcg_solve(A, Md, W.b, tol=1e-16, max_replacements=m if m else 0, spmv_lanes=lanes)
         ref = orc.pcg(W.A, W.b, Mo, tol=1e-16, max_replacements=m)
         assert ref.status == "ENOCONV" and ref.replacements == m
         assert info.status == "ENOCONV" and info.replacements == m, info
@@ -49,12 +54,13 @@ def test_replacement_budget_matches_oracle(gpu, orc, nb):
         assert info.rel_res_true > 1e-16
 
 
-def test_replacement_converges_matches_oracle(gpu, orc):
+@BOTH_SOLVERS
+def test_replacement_converges_matches_oracle(gpu, orc, lanes):
     """tol 1e-14: the recursion meets tol before b - A x does; one
     replacement later both sides converge, with x equal to the oracle's."""
     W = w.workload("poisson2d_32")
     A = dev(W.A)
-    x, info = gpu.pcg_solve(A, gpu.precondition(A, block_size=16), W.b, tol=1e-14)
+    x, info = gpu.pcg_solve(A, gpu.precondition(A, block_size=16), W.b, tol=1e-14, spmv_lanes=lanes)
     ref = orc.pcg(W.A, W.b, orc.Precond.uniform(W.A, 16), tol=1e-14)
     assert ref.status == "OK" and ref.replacements == 1
     assert info.status == "OK" and info.replacements == ref.replacements
@@ -65,8 +71,9 @@ def test_replacement_converges_matches_oracle(gpu, orc):
     assert info.rel_res_true <= 1e-14 and true <= 1.1e-14
 
 
+@BOTH_SOLVERS
 @pytest.mark.parametrize("nb", [16, 0])
-def test_no_replacement_at_max_iter(gpu, orc, nb):
+def test_no_replacement_at_max_iter(gpu, orc, nb, lanes):
     """The recursion meets tol at exactly max_iter while b - A x does not: no
     iteration is left for a restart, so the solve ends ENOCONV at max_iter
     with no replacement, and the residual history (max_iter + 1 entries) is
@@ -76,14 +83,14 @@ def test_no_replacement_at_max_iter(gpu, orc, nb):
     Md = gpu.precondition(A, block_size=nb) if nb else None
     Mo = orc.Precond.uniform(W.A, nb) if nb else None
     tol = 1e-14 if nb else 1e-15
-    _, first = gpu.pcg_solve(A, Md, W.b, tol=tol, max_replacements=0)
+    _, first = gpu.pcg_solve(A, Md, W.b, tol=tol, max_replacements=0, spmv_lanes=lanes)
     assert first.status == "ENOCONV" and first.replacements == 0
     k1 = first.iterations
     guard = 64
     hist = torch.full((k1 + 1 + guard,), float("nan"), dtype=torch.float64, device=DEV)
     for ce in (1, 16):
         hist.fill_(float("nan"))
-        x, info = gpu.pcg_solve(A, Md, W.b, tol=tol, max_iter=k1, check_every=ce, history=hist)
+        x, info = gpu.pcg_solve(A, Md, W.b, tol=tol, max_iter=k1, check_every=ce, history=hist, spmv_lanes=lanes)
         assert info.status == "ENOCONV" and info.iterations == k1 and info.replacements == 0, info
         h = hist.cpu().numpy()
         assert np.all(np.isfinite(h[: k1 + 1])) and np.all(np.isnan(h[k1 + 1:]))
@@ -91,7 +98,7 @@ def test_no_replacement_at_max_iter(gpu, orc, nb):
         assert ref.status == "ENOCONV" and ref.replacements == 0
         assert _rel(x.cpu().numpy(), ref.x) <= 1e-10
     # one iteration more: the replacement happens and the solve continues
-    x, info = gpu.pcg_solve(A, Md, W.b, tol=tol, max_iter=k1 + 1)
+    x, info = gpu.pcg_solve(A, Md, W.b, tol=tol, max_iter=k1 + 1, spmv_lanes=lanes)
     assert info.replacements == 1 and info.iterations == k1 + 1
 
 

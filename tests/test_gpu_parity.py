@@ -234,42 +234,51 @@ def test_pcg_schedules_agree(gpu, orc, lanes):
     _pcg_parity(gpu, orc, W.A, W.b, 64, case="diffusion3d_16/64", spmv_lanes=lanes)
 
 
-def test_pcg_single_block_one_iteration(gpu):
+# spmv_lanes = 0 lets systems of <= 4096 rows take the one-workgroup solver;
+# -1 forces the multi-launch solver (row blocks streamed through LDS)
+BOTH_SOLVERS = pytest.mark.parametrize("lanes", [0, -1], ids=["one-workgroup", "multi-launch"])
+
+
+@BOTH_SOLVERS
+def test_pcg_single_block_one_iteration(gpu, lanes):
     A = w.poisson2d(8)
     b = w.rhs(64, 11)
-    x, info = gpu.pcg_solve(dev(A), gpu.precondition(dev(A), block_size=64), b)
+    x, info = gpu.pcg_solve(dev(A), gpu.precondition(dev(A), block_size=64), b, spmv_lanes=lanes)
     assert info.status == "OK" and info.iterations == 1
     np.testing.assert_allclose(x.cpu().numpy(), np.linalg.solve(A.to_dense(), b), rtol=1e-12)
 
 
-def test_pcg_deterministic(gpu):
+@BOTH_SOLVERS
+def test_pcg_deterministic(gpu, lanes):
     W = w.workload("diffusion3d_16")
     A = dev(W.A)
     M = gpu.precondition(A, block_size=64)
-    x1, i1 = gpu.pcg_solve(A, M, W.b)
-    x2, i2 = gpu.pcg_solve(A, M, W.b)
+    x1, i1 = gpu.pcg_solve(A, M, W.b, spmv_lanes=lanes)
+    x2, i2 = gpu.pcg_solve(A, M, W.b, spmv_lanes=lanes)
     assert i1.iterations == i2.iterations
     assert torch.equal(x1, x2)
 
 
-def test_pcg_edge_cases(gpu):
+@BOTH_SOLVERS
+def test_pcg_edge_cases(gpu, lanes):
     A = w.poisson2d(16)
     Ad = dev(A)
     M = gpu.precondition(Ad, block_size=8)
-    x, info = gpu.pcg_solve(Ad, M, np.zeros(256), x0=np.ones(256))
+    x, info = gpu.pcg_solve(Ad, M, np.zeros(256), x0=np.ones(256), spmv_lanes=lanes)
     assert info.status == "OK" and info.iterations == 0 and torch.all(x == 0)
-    x, info = gpu.pcg_solve(Ad, M, w.rhs(256, 15), max_iter=1)
+    x, info = gpu.pcg_solve(Ad, M, w.rhs(256, 15), max_iter=1, spmv_lanes=lanes)
     assert info.status == "ENOCONV" and info.iterations == 1 and 0 < info.rel_res_true < 1
     b = np.ones(256)
     b[3] = np.nan
-    x, info = gpu.pcg_solve(Ad, M, b)
+    x, info = gpu.pcg_solve(Ad, M, b, spmv_lanes=lanes)
     assert info.status == "ENONFINITE"
     xs = np.linalg.solve(A.to_dense(), w.rhs(256, 16))
-    x, info = gpu.pcg_solve(Ad, M, w.rhs(256, 16), x0=xs)
+    x, info = gpu.pcg_solve(Ad, M, w.rhs(256, 16), x0=xs, spmv_lanes=lanes)
     assert info.status == "OK" and info.iterations == 0
 
 
-def test_pcg_indefinite_breakdown(gpu, orc):
+@BOTH_SOLVERS
+def test_pcg_indefinite_breakdown(gpu, orc, lanes):
     n = 32
     rows, cols, vals = list(range(n)), list(range(n)), [1.0] * n
     for i in range(0, n, 2):
@@ -278,14 +287,16 @@ def test_pcg_indefinite_breakdown(gpu, orc):
     A = w.from_coo(n, np.array(rows), np.array(cols), np.array(vals))
     ev, vec = np.linalg.eigh(A.to_dense())
     Ad = dev(A)
-    x, info = gpu.pcg_solve(Ad, gpu.precondition(Ad, block_size=8), vec[:, 0])
+    x, info = gpu.pcg_solve(Ad, gpu.precondition(Ad, block_size=8), vec[:, 0], spmv_lanes=lanes)
     assert info.status == "EBREAKDOWN" and info.iterations == 0
 
 
-def test_pcg_history_matches_oracle(gpu, orc):
+@BOTH_SOLVERS
+def test_pcg_history_matches_oracle(gpu, orc, lanes):
     W = w.workload("poisson2d_32")
     hist = torch.full((W.A.n + 1,), float("nan"), dtype=torch.float64, device=DEV)
-    x, info = gpu.pcg_solve(dev(W.A), gpu.precondition(dev(W.A), block_size=16), W.b, history=hist)
+    x, info = gpu.pcg_solve(dev(W.A), gpu.precondition(dev(W.A), block_size=16), W.b, history=hist,
+                            spmv_lanes=lanes)
     ref = orc.pcg(W.A, W.b, orc.Precond.uniform(W.A, 16), history=True)
     h = hist[: info.iterations + 1].cpu().numpy()
     k = min(len(h), len(ref.history))
@@ -350,14 +361,15 @@ def test_kappa_many_steps_tiles(gpu, orc):
     assert abs(k.kappa - ko.kappa) <= 1e-6 * ko.kappa
 
 
-def test_pcg_max_iter_iterate_matches_oracle(gpu, orc):
+@BOTH_SOLVERS
+def test_pcg_max_iter_iterate_matches_oracle(gpu, orc, lanes):
     """Stopped after 7 iterations (ENOCONV), the returned x is the 7th iterate,
     x update of the last step included, as in the oracle."""
     W = w.workload("diffusion3d_16")
     M = gpu.precondition(dev(W.A), block_size=64)
     ref = orc.pcg(W.A, W.b, orc.Precond.uniform(W.A, 64), max_iter=7)
     for check_every in (1, 2, 16):
-        x, info = gpu.pcg_solve(dev(W.A), M, W.b, max_iter=7, check_every=check_every)
+        x, info = gpu.pcg_solve(dev(W.A), M, W.b, max_iter=7, check_every=check_every, spmv_lanes=lanes)
         assert info.status == ref.status == "ENOCONV" and info.iterations == ref.iterations == 7
         xg = x.cpu().numpy()
         assert np.linalg.norm(xg - ref.x) / np.linalg.norm(ref.x) <= 1e-12
@@ -377,11 +389,12 @@ def test_pcg_poll_cadence_does_not_change_result(gpu):
         assert torch.equal(x, x0)
 
 
-def test_pcg_warm_start_matches_oracle(gpu, orc):
+@BOTH_SOLVERS
+def test_pcg_warm_start_matches_oracle(gpu, orc, lanes):
     W = w.workload("diffusion3d_16")
     x0 = np.random.default_rng(21).standard_normal(W.A.n)
     M = gpu.precondition(dev(W.A), block_size=64)
-    x, info = gpu.pcg_solve(dev(W.A), M, W.b, x0=x0)
+    x, info = gpu.pcg_solve(dev(W.A), M, W.b, x0=x0, spmv_lanes=lanes)
     ref = orc.pcg(W.A, W.b, orc.Precond.uniform(W.A, 64), x0=x0)
     assert info.status == ref.status == "OK"
     print(f"  it gpu {info.iterations} oracle {ref.iterations}", flush=True)
@@ -545,3 +558,59 @@ def test_duplicates_and_unsorted_columns(gpu, orc, name, make, nb, schedules):
     for lanes in schedules:
         print(f"case {name} lanes={lanes}", flush=True)
         _pcg_parity(gpu, orc, A, b, nb, case=name, spmv_lanes=lanes)
+
+
+SMALL_CASES = [("poisson2d_32/16", lambda: w.workload("poisson2d_32"), 16, None),
+               ("diffusion3d_16/64 (4096 rows, the largest one-workgroup size)", lambda: w.workload("diffusion3d_16"), 64, None),
+               ("random_spd_3001/24 (ragged last block)", lambda: w.random_spd(3001, np.random.default_rng(80)), 24, None),
+               ("random_spd_777 explicit blocks", lambda: w.random_spd(777, np.random.default_rng(81)), 0, "explicit"),
+               ("poisson2d_32 fp32-stored", lambda: w.workload("poisson2d_32"), 16, "fp32"),
+               ("poisson2d_32 plain CG", lambda: w.workload("poisson2d_32"), 0, None)]
+
+
+@pytest.mark.parametrize("name,make,nb,kind", SMALL_CASES, ids=[c[0] for c in SMALL_CASES])
+def test_one_workgroup_solver_matches_oracle(gpu, orc, name, make, nb, kind):
+    """Systems of at most 4096 rows (automatic schedule) are solved in one
+    workgroup: a single host poll, x within 1e-10 of the oracle's, iteration
+    counts within one, and the multi-launch solver on the same system agrees
+    with both."""
+    print(f"case {name}", flush=True)
+    W = make()
+    A_h = W.A if hasattr(W, "A") else W
+    b = W.b if hasattr(W, "b") else w.rhs(A_h.n, 82)
+    Ad = dev(A_h)
+    if kind == "explicit":
+        rng = np.random.default_rng(83)
+        sizes = rng.integers(1, 65, size=A_h.n)
+        off = np.concatenate([[0], np.cumsum(sizes)])
+        off = off[off < A_h.n].tolist() + [A_h.n]
+        Md = gpu.precondition(Ad, offsets=off)
+        Mo = orc.Precond(A_h, off)
+    elif nb:
+        Md = gpu.precondition(Ad, block_size=nb, precision="fp32" if kind == "fp32" else "fp64")
+        Mo = orc.Precond.uniform(A_h, nb)
+    else:
+        Md = Mo = None
+    ref = orc.pcg(A_h, b, Mo)
+    x, info = gpu.pcg_solve(Ad, Md, b)
+    xm, im = gpu.pcg_solve(Ad, Md, b, spmv_lanes=-1)
+    print(f"  it one-workgroup {info.iterations} multi-launch {im.iterations} oracle {ref.iterations}", flush=True)
+    assert info.status == im.status == ref.status == "OK"
+    assert info.polls == 1
+    bar = WIDE_ITERATION_BAR.get(name.split(" ")[0], 1)
+    assert abs(info.iterations - ref.iterations) <= bar and abs(im.iterations - ref.iterations) <= bar
+    for xx in (x, xm):
+        assert _rel(xx.cpu().numpy(), ref.x) <= 1e-10
+    assert info.rel_res_true <= 1e-10
+    true = np.linalg.norm(orc.spmv(A_h, x.cpu().numpy()) - b) / np.linalg.norm(b)
+    assert abs(true - info.rel_res_true) <= 1e-13
+
+
+def test_one_workgroup_limit(gpu):
+    """4097 rows take the multi-launch solver (several polls at the default
+    cadence), 4096 the one-workgroup solver."""
+    for n, one in ((4096, True), (4097, False)):
+        A = w.random_spd(n, np.random.default_rng(n))
+        Ad = dev(A)
+        _, info = gpu.pcg_solve(Ad, gpu.precondition(Ad, block_size=16), w.rhs(n, 84), check_every=1)
+        assert info.status == "OK" and (info.polls == 1) == one, (n, info)
