@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+SMALL_MAX_ROWS = 2048  # systems the library solves in one workgroup (automatic schedule)
 TIMER_STRIDE = 8       # every 8th block-inverse application is timed with events
 
 
@@ -469,8 +470,12 @@ def main():
     # every 8th application is bracketed by events (each event pair delays the
     # launches around it by a few microseconds, which would otherwise be
     # charged to the solve being timed)
+    # (systems the one-workgroup solver takes, n <= SMALL_MAX_ROWS, have no
+    # separate application launch to time: their roofline is the whole solve's)
     cap = 4096
-    timers = [bjp.KernelTimer(bjp.KERNEL_APPLY, cap, stride=TIMER_STRIDE) for _ in range(args.steps)]
+    small = W.A.n <= SMALL_MAX_ROWS
+    timers = [None if small else bjp.KernelTimer(bjp.KERNEL_APPLY, cap, stride=TIMER_STRIDE)
+              for _ in range(args.steps)]
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
@@ -493,16 +498,22 @@ def main():
         assert r[2].status == "OK" and r[3].status == "OK"
 
     value = sum(iters) / (sum(pcg_ms) / 1e3)
-    durs = []
-    for tmr, r in zip(timers, results):
-        # launches past the converged iteration return at once: leave them out
-        durs.extend(tmr.durations_ms()[: -(-r[1].iterations // TIMER_STRIDE)])
-    apply_avg_ms = float(np.mean(durs))
     off = M.offsets()
     elem = 4 if M.precision == bjp.FP32_STORE else 8
     ab = apply_bytes(W.A.n, off, elem)
-    achieved = ab / (apply_avg_ms * 1e-3) / 1e9
     B_iter = ab + spmv_bytes(W.A.n, W.A.nnz, column_bytes(W.A)) + direction_bytes(W.A.n)
+    durs = []
+    if small:
+        # one launch per solve: the whole iteration's bytes over its time
+        kernel, per_launch = "k_pcg_small (the whole solve in one workgroup; latency-bound)", B_iter
+        apply_avg_ms = sum(pcg_ms) / sum(iters)
+    else:
+        for tmr, r in zip(timers, results):
+            # launches past the converged iteration return at once: leave them out
+            durs.extend(tmr.durations_ms()[: -(-r[1].iterations // TIMER_STRIDE)])
+        kernel, per_launch = "k_apply (block inverse + r update)", ab
+        apply_avg_ms = float(np.mean(durs))
+    achieved = per_launch / (apply_avg_ms * 1e-3) / 1e9
     iter_gbs = B_iter * sum(iters) / (sum(pcg_ms) / 1e3) / 1e9
     traffic = read_traffic(f"apply_{args.workload}")
     m_bytes = ab - 32 * W.A.n          # packed inverses + offsets
@@ -538,12 +549,13 @@ def main():
         "kappa_A": kA.kappa,
         "kappa_MA": kM.kappa,
         "rel_res_true": info.rel_res_true,
-        "roofline": {"bound": "hbm", "kernel": "k_apply (block inverse + r update)",
+        "roofline": {"bound": "hbm", "kernel": kernel,
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "traffic_source": (f"profiles/apply_{args.workload}_counters.md (rocprofv3 FETCH_SIZE/"
                                         "WRITE_SIZE taken on the same kernel sources)" if traffic else None),
-                     "bytes_per_launch": ab, "avg_launch_us": round(apply_avg_ms * 1e3, 3),
+                     "bytes_per_launch": per_launch,
+                     "avg_launch_us" if not small else "us_per_iteration": round(apply_avg_ms * 1e3, 3),
                      "launches_timed": len(durs)},
         "kappa_roofline": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
                            "bytes_A": kb_A, "bytes_MA": kb_M,

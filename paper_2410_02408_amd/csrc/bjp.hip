@@ -264,21 +264,24 @@ void launch_apply(const bjp_precond_t *M, int grid, const ApplyArgs &a, hipStrea
     else launch_apply_t<double, MODE>(M->group, grid, a, s);
 }
 
+// The one-workgroup solver keeps two n-vectors in LDS (16 n bytes).
 template <typename TS>
 void launch_small_t(int G, const SmallArgs &a, hipStream_t s) {
+    const size_t lds = 2 * sizeof(double) * (size_t)a.n;
     switch (G) {
-        case 1: hipLaunchKernelGGL((k_pcg_small<1, TS, true>), dim3(1), dim3(kSmallWG), 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_pcg_small<2, TS, true>), dim3(1), dim3(kSmallWG), 0, s, a); break;
-        case 4: hipLaunchKernelGGL((k_pcg_small<4, TS, true>), dim3(1), dim3(kSmallWG), 0, s, a); break;
-        case 8: hipLaunchKernelGGL((k_pcg_small<8, TS, true>), dim3(1), dim3(kSmallWG), 0, s, a); break;
-        case 16: hipLaunchKernelGGL((k_pcg_small<16, TS, true>), dim3(1), dim3(kSmallWG), 0, s, a); break;
-        case 32: hipLaunchKernelGGL((k_pcg_small<32, TS, true>), dim3(1), dim3(kSmallWG), 0, s, a); break;
-        default: hipLaunchKernelGGL((k_pcg_small<64, TS, true>), dim3(1), dim3(kSmallWG), 0, s, a); break;
+        case 1: hipLaunchKernelGGL((k_pcg_small<1, TS, true>), dim3(1), dim3(kSmallWG), lds, s, a); break;
+        case 2: hipLaunchKernelGGL((k_pcg_small<2, TS, true>), dim3(1), dim3(kSmallWG), lds, s, a); break;
+        case 4: hipLaunchKernelGGL((k_pcg_small<4, TS, true>), dim3(1), dim3(kSmallWG), lds, s, a); break;
+        case 8: hipLaunchKernelGGL((k_pcg_small<8, TS, true>), dim3(1), dim3(kSmallWG), lds, s, a); break;
+        case 16: hipLaunchKernelGGL((k_pcg_small<16, TS, true>), dim3(1), dim3(kSmallWG), lds, s, a); break;
+        case 32: hipLaunchKernelGGL((k_pcg_small<32, TS, true>), dim3(1), dim3(kSmallWG), lds, s, a); break;
+        default: hipLaunchKernelGGL((k_pcg_small<64, TS, true>), dim3(1), dim3(kSmallWG), lds, s, a); break;
     }
 }
 
 void launch_small(const bjp_precond_t *M, const SmallArgs &a, hipStream_t s) {
-    if (!M) hipLaunchKernelGGL((k_pcg_small<1, double, false>), dim3(1), dim3(kSmallWG), 0, s, a);
+    const size_t lds = 2 * sizeof(double) * (size_t)a.n;
+    if (!M) hipLaunchKernelGGL((k_pcg_small<1, double, false>), dim3(1), dim3(kSmallWG), lds, s, a);
     else if (M->precision == BJP_FP32_STORE) launch_small_t<float>(M->group, a, s);
     else launch_small_t<double>(M->group, a, s);
 }
@@ -820,10 +823,6 @@ int pcg_solve_impl(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, 
         sm.val = A->val;
         sm.b = b;
         sm.x = x;
-        sm.r = r;
-        sm.z = z;
-        sm.p = p0;
-        sm.q = q;
         if (M) {
             sm.nblocks = M->num_blocks;
             sm.num_packets = M->num_packets;

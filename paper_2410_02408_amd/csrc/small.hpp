@@ -7,11 +7,13 @@
 // scalar decisions (finish_decide) and stopping rule, true-residual check and
 // residual replacement as bjp_pcg_solve, with workgroup barriers between the
 // phases instead of kernel boundaries.  Thread t owns rows t, t + kSmallWG,
-// ...: it forms their products row by row (entries in storage order), their
-// x, r and p updates; the block-inverse application runs packet by packet on
-// the waves (wave w takes packets w, w + kSmallWaves, ...).  Every total is a
-// fixed-order workgroup reduction, so the solve is deterministic.  The
-// vectors live in the solver's workspace and stay in the caches.
+// ...: it keeps their x, r, p in registers, forms their products row by
+// row (entries in storage order) gathering from the direction held in LDS;
+// the block-inverse application runs packet by packet on the waves (wave w
+// takes packets w, w + kSmallWaves, ...) on r staged in LDS.  Every total is
+// a fixed-order workgroup reduction, so the solve is deterministic.  Only the
+// matrix and the block inverses are read from memory (from the caches) in an
+// iteration.
 #pragma once
 
 #include "blocks.hpp"
@@ -22,7 +24,7 @@ namespace bjp {
 
 constexpr int kSmallWG = 512;
 constexpr int kSmallWaves = kSmallWG / 64;
-constexpr int kSmallMaxRows = 8 * kSmallWG;   // at most 8 rows per thread
+constexpr int kSmallMaxRows = 4 * kSmallWG;   // at most 4 rows per thread
 constexpr int kSmallMaxMeanRow = 32;          // longer rows take the multi-launch products
 
 struct SmallArgs {
@@ -31,7 +33,6 @@ struct SmallArgs {
     const double *val;
     const double *b;
     double *x;
-    double *r, *z, *p, *q;   // z == r without a preconditioner
     // the preconditioner (unused without one)
     int nblocks, num_packets, uniform_nb;
     const int32_t *off;
@@ -64,17 +65,14 @@ __device__ __forceinline__ void small_sum(double (&v)[NQ], double (*red)[kSmallW
     __syncthreads();
 }
 
-// (A u)_i, entries in storage order.
-__device__ __forceinline__ double small_row(const SmallArgs &a, int i, const double *u) {
-    double s = 0.0;
-    const int k1 = a.rp[i + 1];
-    for (int k = a.rp[i]; k < k1; ++k) s += a.val[k] * u[a.ci[k]];
-    return s;
-}
+// This thread's rows: row(u) = threadIdx.x + u * kSmallWG, u < kSmallR.
+constexpr int kSmallR = kSmallMaxRows / kSmallWG;
 
-// z = M^-1 r over every packet; this thread's share of r^T z and r^T r.
+// z = M^-1 r over every packet, in place in w (r in, z out; each row is read
+// and written by the one lane that owns it in its packet); this thread's
+// share of r^T z and r^T r.
 template <int G, typename TS>
-__device__ __forceinline__ void small_apply(const SmallArgs &a, double &rz, double &rr) {
+__device__ __forceinline__ void small_apply(const SmallArgs &a, double *w, double &rz, double &rr) {
     constexpr int P = 64 / G, E = packet_elems(G);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane / G, i = lane % G;
@@ -92,23 +90,45 @@ __device__ __forceinline__ void small_apply(const SmallArgs &a, double &rz, doub
         }
         const bool act = i < nn;
         const int rc = min(s + i, a.n - 1);
-        const double rv = act ? a.r[rc] : 0.0;
         TS dv[G / 2 + 1];
         packet_load<G, TS>(tiles + (size_t)pk * E, lane, g, i, dv);
+        const double rv = act ? w[rc] : 0.0;
         const TS zv = packet_product<G, TS>(dv, g, i, nn, (TS)rv);
         if (act) {
             const double z = (double)zv;
-            a.z[s + i] = z;
+            w[s + i] = z;
             rz += rv * z;
             rr += rv * rv;
         }
     }
 }
 
+// The vectors live in LDS and registers: u (the vector the products gather:
+// p, or x for a residual) and w (r before an application, z after it), n
+// doubles each; every thread keeps x, r and p of its own rows in registers
+// (q = A p of its rows goes to w, which is free until the next application)
+// and the extents of its rows' CSR entries.
 template <int G, typename TS, bool HAS_M>
 __global__ __launch_bounds__(kSmallWG) void k_pcg_small(SmallArgs a) {
+    extern __shared__ double lds[];
+    double *u = lds, *w = lds + a.n;
     __shared__ double red[2][kSmallWaves];
     const int tid = threadIdx.x, n = a.n;
+    int kb[kSmallR], ke[kSmallR];
+    double x[kSmallR], r[kSmallR], p[kSmallR];
+#pragma unroll
+    for (int k = 0; k < kSmallR; ++k) {
+        const int i = tid + k * kSmallWG;
+        kb[k] = i < n ? a.rp[i] : 0;
+        ke[k] = i < n ? a.rp[i + 1] : 0;
+        x[k] = r[k] = p[k] = 0.0;
+    }
+    // (A u) of this thread's row k, entries in storage order
+    auto row = [&](int k) {
+        double acc = 0.0;
+        for (int e = kb[k]; e < ke[k]; ++e) acc += a.val[e] * u[a.ci[e]];
+        return acc;
+    };
     PcgState L;
     L.rho = L.alpha = L.beta = L.bnorm2 = 0.0;
     L.tol = a.tol;
@@ -124,83 +144,143 @@ __global__ __launch_bounds__(kSmallWG) void k_pcg_small(SmallArgs a) {
 
     // r = b - A x0 (x0 = 0 unless given), ||b||^2, ||r||^2
     {
+#pragma unroll
+        for (int k = 0; k < kSmallR; ++k) {
+            const int i = tid + k * kSmallWG;
+            if (i < n) {
+                x[k] = a.x0_given ? a.x[i] : 0.0;
+                u[i] = x[k];
+            }
+        }
+        __syncthreads();
         double v[2] = {0.0, 0.0};
-        for (int i = tid; i < n; i += kSmallWG) {
-            const double bi = a.b[i];
-            double ri = bi;
-            if (a.x0_given) ri = bi - small_row(a, i, a.x);
-            else a.x[i] = 0.0;
-            a.r[i] = ri;
-            v[0] += bi * bi;
-            v[1] += ri * ri;
+#pragma unroll
+        for (int k = 0; k < kSmallR; ++k) {
+            const int i = tid + k * kSmallWG;
+            if (i < n) {
+                const double bi = a.b[i];
+                r[k] = a.x0_given ? bi - row(k) : bi;
+                v[0] += bi * bi;
+                v[1] += r[k] * r[k];
+            }
         }
         small_sum<2>(v, red);
         finish_decide<FIN_RESID_START>(f, &L, nullptr, v);
     }
+    // w = r, z = M^-1 r in w; this thread's share of r^T z (and r^T r)
+    auto precondition = [&](double &rz, double &rr) {
+        if constexpr (HAS_M) {
+#pragma unroll
+            for (int k = 0; k < kSmallR; ++k) {
+                const int i = tid + k * kSmallWG;
+                if (i < n) w[i] = r[k];
+            }
+            __syncthreads();   // r complete before the packets read it
+            small_apply<G, TS>(a, w, rz, rr);
+        } else {
+#pragma unroll
+            for (int k = 0; k < kSmallR; ++k) {
+                const int i = tid + k * kSmallWG;
+                if (i < n) {
+                    w[i] = r[k];
+                    rz += r[k] * r[k];
+                }
+            }
+            rr = rz;
+        }
+    };
     int repl = 0;
     for (;;) {
         if (!L.done) {
             // (re)start the direction from r: z = M^-1 r, rho = r^T z, p = z
             double v[1] = {0.0};
-            if constexpr (HAS_M) {
-                double rr = 0.0;
-                small_apply<G, TS>(a, v[0], rr);
-            } else {
-                for (int i = tid; i < n; i += kSmallWG) v[0] += a.r[i] * a.r[i];
-            }
+            double rr = 0.0;
+            precondition(v[0], rr);
             small_sum<1>(v, red);
             finish_decide<FIN_PCG_START>(f, &L, nullptr, v);
-            if (!L.done)
-                for (int i = tid; i < n; i += kSmallWG) a.p[i] = a.z[i];
+            if (!L.done) {
+#pragma unroll
+                for (int k = 0; k < kSmallR; ++k) {
+                    const int i = tid + k * kSmallWG;
+                    if (i < n) {
+                        p[k] = w[i];
+                        u[i] = p[k];
+                    }
+                }
+            }
         }
         while (!L.done) {
-            __syncthreads();   // p complete before it is gathered
+            __syncthreads();   // p complete in u before it is gathered
+            // q = A p, parked in w (free until the next application) by its owner
             double sg[1] = {0.0};
-            for (int i = tid; i < n; i += kSmallWG) {
-                const double qi = small_row(a, i, a.p);
-                a.q[i] = qi;
-                sg[0] += a.p[i] * qi;
+#pragma unroll
+            for (int k = 0; k < kSmallR; ++k) {
+                const int i = tid + k * kSmallWG;
+                if (i < n) {
+                    const double qi = row(k);
+                    w[i] = qi;
+                    sg[0] += p[k] * qi;
+                }
             }
             small_sum<1>(sg, red);
             finish_decide<FIN_SIGMA>(f, &L, nullptr, sg);
             if (L.done) break;
             const double alpha = L.alpha;
-            for (int i = tid; i < n; i += kSmallWG) {
-                a.x[i] = __builtin_fma(alpha, a.p[i], a.x[i]);
-                a.r[i] = __builtin_fma(-alpha, a.q[i], a.r[i]);
+#pragma unroll
+            for (int k = 0; k < kSmallR; ++k) {
+                const int i = tid + k * kSmallWG;
+                if (i < n) {
+                    x[k] = __builtin_fma(alpha, p[k], x[k]);
+                    r[k] = __builtin_fma(-alpha, w[i], r[k]);
+                }
             }
+            double t[2] = {0.0, 0.0};
+            precondition(t[0], t[1]);
             if constexpr (HAS_M) {
-                double u[2] = {0.0, 0.0};
-                __syncthreads();   // r complete before the packets read it
-                small_apply<G, TS>(a, u[0], u[1]);
-                small_sum<2>(u, red);
-                finish_decide<FIN_PCG_UPDATE>(f, &L, nullptr, u);
+                small_sum<2>(t, red);
+                finish_decide<FIN_PCG_UPDATE>(f, &L, nullptr, t);
             } else {
-                double u[1] = {0.0};
-                for (int i = tid; i < n; i += kSmallWG) u[0] += a.r[i] * a.r[i];
-                small_sum<1>(u, red);
-                finish_decide<FIN_PCG_UPDATE_I>(f, &L, nullptr, u);
+                double t1[1] = {t[0]};
+                small_sum<1>(t1, red);
+                finish_decide<FIN_PCG_UPDATE_I>(f, &L, nullptr, t1);
             }
             if (!L.done) {
                 const double beta = L.beta;
-                for (int i = tid; i < n; i += kSmallWG) a.p[i] = __builtin_fma(beta, a.p[i], a.z[i]);
+#pragma unroll
+                for (int k = 0; k < kSmallR; ++k) {
+                    const int i = tid + k * kSmallWG;
+                    if (i < n) {
+                        p[k] = __builtin_fma(beta, p[k], w[i]);
+                        u[i] = p[k];
+                    }
+                }
             }
         }
         if (L.zero_rhs) {
-            for (int i = tid; i < n; i += kSmallWG) a.x[i] = 0.0;
+#pragma unroll
+            for (int k = 0; k < kSmallR; ++k) x[k] = 0.0;
             L.relres_true = 0.0;
             break;
         }
         // the true residual r = b - A x (also the residual a replacement restarts from)
-        __syncthreads();   // x complete before it is gathered
+        __syncthreads();   // every gather of u is done before x replaces p there
+#pragma unroll
+        for (int k = 0; k < kSmallR; ++k) {
+            const int i = tid + k * kSmallWG;
+            if (i < n) u[i] = x[k];
+        }
+        __syncthreads();
         {
             double v[2] = {0.0, 0.0};
-            for (int i = tid; i < n; i += kSmallWG) {
-                const double bi = a.b[i];
-                const double ri = bi - small_row(a, i, a.x);
-                a.r[i] = ri;
-                v[0] += bi * bi;
-                v[1] += ri * ri;
+#pragma unroll
+            for (int k = 0; k < kSmallR; ++k) {
+                const int i = tid + k * kSmallWG;
+                if (i < n) {
+                    const double bi = a.b[i];
+                    r[k] = bi - row(k);
+                    v[0] += bi * bi;
+                    v[1] += r[k] * r[k];
+                }
             }
             small_sum<2>(v, red);
             finish_decide<FIN_RESID_TRUE>(f, &L, nullptr, v);
@@ -213,6 +293,11 @@ __global__ __launch_bounds__(kSmallWG) void k_pcg_small(SmallArgs a) {
         }
         ++repl;
         L.done = 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kSmallR; ++k) {
+        const int i = tid + k * kSmallWG;
+        if (i < n) a.x[i] = x[k];
     }
     if (tid == 0) {
         store_state(a.out, L);

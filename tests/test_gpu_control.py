@@ -22,7 +22,7 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-# spmv_lanes = 0: the one-workgroup solver (1024 rows); -1: the multi-launch solver
+# spmv_lanes = 0: the one-workgroup solver (these systems have 1024 rows); -1: the multi-launch solver
 BOTH_SOLVERS = pytest.mark.parametrize("lanes", [0, -1], ids=["one-workgroup", "multi-launch"])
 
 

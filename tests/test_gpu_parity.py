@@ -234,8 +234,9 @@ def test_pcg_schedules_agree(gpu, orc, lanes):
     _pcg_parity(gpu, orc, W.A, W.b, 64, case="diffusion3d_16/64", spmv_lanes=lanes)
 
 
-# spmv_lanes = 0 lets systems of <= 4096 rows take the one-workgroup solver;
-# -1 forces the multi-launch solver (row blocks streamed through LDS)
+# spmv_lanes = 0 lets systems of <= 2048 rows take the one-workgroup solver;
+# -1 forces the multi-launch solver (row blocks streamed through LDS).  The
+# tests run on both use systems of at most 2048 rows (3D: 12^3 = 1728).
 BOTH_SOLVERS = pytest.mark.parametrize("lanes", [0, -1], ids=["one-workgroup", "multi-launch"])
 
 
@@ -250,7 +251,7 @@ def test_pcg_single_block_one_iteration(gpu, lanes):
 
 @BOTH_SOLVERS
 def test_pcg_deterministic(gpu, lanes):
-    W = w.workload("diffusion3d_16")
+    W = w.workload("diffusion3d_12")
     A = dev(W.A)
     M = gpu.precondition(A, block_size=64)
     x1, i1 = gpu.pcg_solve(A, M, W.b, spmv_lanes=lanes)
@@ -365,7 +366,7 @@ def test_kappa_many_steps_tiles(gpu, orc):
 def test_pcg_max_iter_iterate_matches_oracle(gpu, orc, lanes):
     """Stopped after 7 iterations (ENOCONV), the returned x is the 7th iterate,
     x update of the last step included, as in the oracle."""
-    W = w.workload("diffusion3d_16")
+    W = w.workload("diffusion3d_12")
     M = gpu.precondition(dev(W.A), block_size=64)
     ref = orc.pcg(W.A, W.b, orc.Precond.uniform(W.A, 64), max_iter=7)
     for check_every in (1, 2, 16):
@@ -391,14 +392,14 @@ def test_pcg_poll_cadence_does_not_change_result(gpu):
 
 @BOTH_SOLVERS
 def test_pcg_warm_start_matches_oracle(gpu, orc, lanes):
-    W = w.workload("diffusion3d_16")
+    W = w.workload("diffusion3d_12")
     x0 = np.random.default_rng(21).standard_normal(W.A.n)
     M = gpu.precondition(dev(W.A), block_size=64)
     x, info = gpu.pcg_solve(dev(W.A), M, W.b, x0=x0, spmv_lanes=lanes)
     ref = orc.pcg(W.A, W.b, orc.Precond.uniform(W.A, 64), x0=x0)
     assert info.status == ref.status == "OK"
     print(f"  it gpu {info.iterations} oracle {ref.iterations}", flush=True)
-    assert abs(info.iterations - ref.iterations) <= WIDE_ITERATION_BAR.get("diffusion3d_16/64 warm", 1)
+    assert abs(info.iterations - ref.iterations) <= WIDE_ITERATION_BAR.get("diffusion3d_12/64 warm", 1)
     assert np.linalg.norm(x.cpu().numpy() - ref.x) / np.linalg.norm(ref.x) <= 1e-10
 
 
@@ -561,8 +562,9 @@ def test_duplicates_and_unsorted_columns(gpu, orc, name, make, nb, schedules):
 
 
 SMALL_CASES = [("poisson2d_32/16", lambda: w.workload("poisson2d_32"), 16, None),
-               ("diffusion3d_16/64 (4096 rows, the largest one-workgroup size)", lambda: w.workload("diffusion3d_16"), 64, None),
-               ("random_spd_3001/24 (ragged last block)", lambda: w.random_spd(3001, np.random.default_rng(80)), 24, None),
+               ("diffusion3d_12/64 (1728 rows)", lambda: w.workload("diffusion3d_12"), 64, None),
+               ("random_spd_2048/64 (the largest one-workgroup size)", lambda: w.random_spd(2048, np.random.default_rng(79)), 64, None),
+               ("random_spd_2001/24 (ragged last block)", lambda: w.random_spd(2001, np.random.default_rng(80)), 24, None),
                ("random_spd_777 explicit blocks", lambda: w.random_spd(777, np.random.default_rng(81)), 0, "explicit"),
                ("poisson2d_32 fp32-stored", lambda: w.workload("poisson2d_32"), 16, "fp32"),
                ("poisson2d_32 plain CG", lambda: w.workload("poisson2d_32"), 0, None)]
@@ -570,7 +572,7 @@ SMALL_CASES = [("poisson2d_32/16", lambda: w.workload("poisson2d_32"), 16, None)
 
 @pytest.mark.parametrize("name,make,nb,kind", SMALL_CASES, ids=[c[0] for c in SMALL_CASES])
 def test_one_workgroup_solver_matches_oracle(gpu, orc, name, make, nb, kind):
-    """Systems of at most 4096 rows (automatic schedule) are solved in one
+    """Systems of at most 2048 rows (automatic schedule) are solved in one
     workgroup: a single host poll, x within 1e-10 of the oracle's, iteration
     counts within one, and the multi-launch solver on the same system agrees
     with both."""
@@ -607,9 +609,9 @@ def test_one_workgroup_solver_matches_oracle(gpu, orc, name, make, nb, kind):
 
 
 def test_one_workgroup_limit(gpu):
-    """4097 rows take the multi-launch solver (several polls at the default
-    cadence), 4096 the one-workgroup solver."""
-    for n, one in ((4096, True), (4097, False)):
+    """2049 rows take the multi-launch solver (several polls at a cadence of
+    one iteration), 2048 the one-workgroup solver."""
+    for n, one in ((2048, True), (2049, False)):
         A = w.random_spd(n, np.random.default_rng(n))
         Ad = dev(A)
         _, info = gpu.pcg_solve(Ad, gpu.precondition(Ad, block_size=16), w.rhs(n, 84), check_every=1)
