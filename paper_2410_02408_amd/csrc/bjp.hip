@@ -286,6 +286,28 @@ void launch_small(const bjp_precond_t *M, const SmallArgs &a, hipStream_t s) {
     else launch_small_t<double>(M->group, a, s);
 }
 
+// The one-workgroup Lanczos keeps two n-vectors and the step's Gram
+// coefficients in LDS.
+template <typename TS>
+void launch_lanczos_small_t(int G, const LanczosSmallArgs &a, size_t lds, hipStream_t s) {
+    switch (G) {
+        case 1: hipLaunchKernelGGL((k_lanczos_small<1, TS, true>), dim3(1), dim3(kSmallWG), lds, s, a); break;
+        case 2: hipLaunchKernelGGL((k_lanczos_small<2, TS, true>), dim3(1), dim3(kSmallWG), lds, s, a); break;
+        case 4: hipLaunchKernelGGL((k_lanczos_small<4, TS, true>), dim3(1), dim3(kSmallWG), lds, s, a); break;
+        case 8: hipLaunchKernelGGL((k_lanczos_small<8, TS, true>), dim3(1), dim3(kSmallWG), lds, s, a); break;
+        case 16: hipLaunchKernelGGL((k_lanczos_small<16, TS, true>), dim3(1), dim3(kSmallWG), lds, s, a); break;
+        case 32: hipLaunchKernelGGL((k_lanczos_small<32, TS, true>), dim3(1), dim3(kSmallWG), lds, s, a); break;
+        default: hipLaunchKernelGGL((k_lanczos_small<64, TS, true>), dim3(1), dim3(kSmallWG), lds, s, a); break;
+    }
+}
+
+void launch_lanczos_small(const bjp_precond_t *M, const LanczosSmallArgs &a, hipStream_t s) {
+    const size_t lds = sizeof(double) * (2 * (size_t)a.n + (size_t)a.steps + 1);
+    if (!M) hipLaunchKernelGGL((k_lanczos_small<1, double, false>), dim3(1), dim3(kSmallWG), lds, s, a);
+    else if (M->precision == BJP_FP32_STORE) launch_lanczos_small_t<float>(M->group, a, lds, s);
+    else launch_lanczos_small_t<double>(M->group, a, lds, s);
+}
+
 // gs = lanes per row of the lane-group schedule; 0 = row-block streaming with
 // stages of 4 entries per thread, kStream7 = with stages of 7.
 constexpr int kStream7 = -7;
@@ -1247,88 +1269,115 @@ int bjp_kappa_estimate(const bjp_csr_t *A, const bjp_precond_t *M, const double 
     int s = run_validate(A, flags, stream);
     if (s != BJP_OK) return fail(s);
 
-    const int gs = auto_spmv(A);
-    const RowLaunch Ls = spmv_shape(n, gs);
-    const RowLaunch Lr = rows_shape(n);
-    hipLaunchKernelGGL(k_lanczos_state_init, dim3(1), dim3(64), 0, stream, ls, steps);
-    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, stream, zeros, 8, 0.0);
-    HIP_TRY(hipMemcpyAsync(rt, v0, sizeof(double) * n, hipMemcpyDeviceToDevice, stream));
-
-    ApplyArgs aa{};
-    aa.n = n;
-    if (M) {
-        aa.nblocks = M->num_blocks;
-        aa.num_packets = M->num_packets;
-        aa.uniform_nb = M->block_size;
-        aa.off = M->offsets;
-        aa.tiles = M->tiles;
-    }
-    const RowLaunch La = M ? apply_shape(M) : Lr;
-    aa.rin = rt;
-    aa.zout = zt;
-    aa.ls = ls;
-    aa.partials = partials;
-    FinishArgs fl{};
-    fl.ls = ls;
-    fl.partials = partials;
-    fl.alpha_out = al;
-    fl.beta_out = be;
-    if (M) launch_apply<APPLY_PLAIN>(M, La.grid, aa, stream);
-    hipLaunchKernelGGL(k_lanczos_start, dim3(Lr.grid), dim3(kWG), 0, stream, ls, rt, zt, n, Lr.chunk,
-                       partials);
-    finish<FIN_LZ_START>(fl, Lr.grid, stream);
-
-    SpmvArgs sa{};
-    sa.n = n;
-    sa.chunk = Ls.chunk;
-    sa.rp = A->row_ptr;
-    sa.ci = A->nnz > 0 ? A->col_idx : reinterpret_cast<const int32_t *>(zeros);
-    sa.val = A->nnz > 0 ? A->val : zeros;
-    sa.ls = ls;
-    sa.zt = zt;
-    sa.rt = rt;
-    sa.V = V;
-    sa.U = U;
-    sa.ld = ld;
-    sa.w = w;
-    sa.has_m = M ? 1 : 0;
-    sa.partials = partials;
-
-    GramArgs ga{};
-    ga.n = n;
-    ga.chunk = Lg.chunk;
-    ga.ls = ls;
-    ga.w = w;
-    ga.U = U;
-    ga.V = V;
-    ga.ld = ld;
-    ga.rt = rt;
-    ga.c = c;
-    ga.cpart = cpart;
-    ga.ldc = steps + 1;
-    ga.has_m = M ? 1 : 0;
-    ga.partials = partials;
-
     LanczosState h{};
-    for (int j = 0; j < steps; ++j) {
-        launch_spmv<SPMV_LANCZOS>(gs, Ls.grid, sa, stream);
-        finish<FIN_LZ_ALPHA>(fl, Ls.grid, stream);
-        hipLaunchKernelGGL((k_gram<GRAM_FIRST>), dim3(Lg.grid), dim3(kWG), 0, stream, ga);
-        hipLaunchKernelGGL(k_gram_reduce, dim3(j + 1), dim3(kWG), 0, stream, ls, cpart, steps + 1, Lg.grid, c);
-        hipLaunchKernelGGL((k_gram<GRAM_SECOND>), dim3(Lg.grid), dim3(kWG), 0, stream, ga);
-        hipLaunchKernelGGL(k_gram_reduce, dim3(j + 1), dim3(kWG), 0, stream, ls, cpart, steps + 1, Lg.grid, c);
-        hipLaunchKernelGGL((k_gram<GRAM_FINAL>), dim3(Lg.grid), dim3(kWG), 0, stream, ga);
+    // Small systems: the whole estimate in one workgroup (small.hpp), the same
+    // steps and decisions.
+    if (n <= kSmallMaxRows && (long long)A->nnz <= (long long)kSmallMaxMeanRow * n && steps <= kSmallMaxSteps) {
+        LanczosSmallArgs la{};
+        la.n = n;
+        la.rp = A->row_ptr;
+        la.ci = A->col_idx;
+        la.val = A->val;
         if (M) {
-            launch_apply<APPLY_LANCZOS>(M, La.grid, aa, stream);
-            finish<FIN_LZ_BETA>(fl, La.grid, stream);
-        } else {
-            finish<FIN_LZ_BETA>(fl, Lg.grid, stream);
+            la.nblocks = M->num_blocks;
+            la.num_packets = M->num_packets;
+            la.uniform_nb = M->block_size;
+            la.off = M->offsets;
+            la.tiles = M->tiles;
         }
+        la.v0 = v0;
+        la.steps = steps;
+        la.U = U;
+        la.V = V;
+        la.ld = ld;
+        la.alpha = al;
+        la.beta = be;
+        la.ls = ls;
+        launch_lanczos_small(M, la, stream);
         HIP_TRY(hipGetLastError());
-        if ((j & 31) == 31 && j + 1 < steps) {
-            HIP_TRY(hipMemcpyAsync(&h, ls, sizeof(h), hipMemcpyDeviceToHost, stream));
-            HIP_TRY(hipStreamSynchronize(stream));
-            if (h.done) break;
+    } else {
+        const int gs = auto_spmv(A);
+        const RowLaunch Ls = spmv_shape(n, gs);
+        const RowLaunch Lr = rows_shape(n);
+        hipLaunchKernelGGL(k_lanczos_state_init, dim3(1), dim3(64), 0, stream, ls, steps);
+        hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, stream, zeros, 8, 0.0);
+        HIP_TRY(hipMemcpyAsync(rt, v0, sizeof(double) * n, hipMemcpyDeviceToDevice, stream));
+
+        ApplyArgs aa{};
+        aa.n = n;
+        if (M) {
+            aa.nblocks = M->num_blocks;
+            aa.num_packets = M->num_packets;
+            aa.uniform_nb = M->block_size;
+            aa.off = M->offsets;
+            aa.tiles = M->tiles;
+        }
+        const RowLaunch La = M ? apply_shape(M) : Lr;
+        aa.rin = rt;
+        aa.zout = zt;
+        aa.ls = ls;
+        aa.partials = partials;
+        FinishArgs fl{};
+        fl.ls = ls;
+        fl.partials = partials;
+        fl.alpha_out = al;
+        fl.beta_out = be;
+        if (M) launch_apply<APPLY_PLAIN>(M, La.grid, aa, stream);
+        hipLaunchKernelGGL(k_lanczos_start, dim3(Lr.grid), dim3(kWG), 0, stream, ls, rt, zt, n, Lr.chunk,
+                           partials);
+        finish<FIN_LZ_START>(fl, Lr.grid, stream);
+
+        SpmvArgs sa{};
+        sa.n = n;
+        sa.chunk = Ls.chunk;
+        sa.rp = A->row_ptr;
+        sa.ci = A->nnz > 0 ? A->col_idx : reinterpret_cast<const int32_t *>(zeros);
+        sa.val = A->nnz > 0 ? A->val : zeros;
+        sa.ls = ls;
+        sa.zt = zt;
+        sa.rt = rt;
+        sa.V = V;
+        sa.U = U;
+        sa.ld = ld;
+        sa.w = w;
+        sa.has_m = M ? 1 : 0;
+        sa.partials = partials;
+
+        GramArgs ga{};
+        ga.n = n;
+        ga.chunk = Lg.chunk;
+        ga.ls = ls;
+        ga.w = w;
+        ga.U = U;
+        ga.V = V;
+        ga.ld = ld;
+        ga.rt = rt;
+        ga.c = c;
+        ga.cpart = cpart;
+        ga.ldc = steps + 1;
+        ga.has_m = M ? 1 : 0;
+        ga.partials = partials;
+
+        for (int j = 0; j < steps; ++j) {
+            launch_spmv<SPMV_LANCZOS>(gs, Ls.grid, sa, stream);
+            finish<FIN_LZ_ALPHA>(fl, Ls.grid, stream);
+            hipLaunchKernelGGL((k_gram<GRAM_FIRST>), dim3(Lg.grid), dim3(kWG), 0, stream, ga);
+            hipLaunchKernelGGL(k_gram_reduce, dim3(j + 1), dim3(kWG), 0, stream, ls, cpart, steps + 1, Lg.grid, c);
+            hipLaunchKernelGGL((k_gram<GRAM_SECOND>), dim3(Lg.grid), dim3(kWG), 0, stream, ga);
+            hipLaunchKernelGGL(k_gram_reduce, dim3(j + 1), dim3(kWG), 0, stream, ls, cpart, steps + 1, Lg.grid, c);
+            hipLaunchKernelGGL((k_gram<GRAM_FINAL>), dim3(Lg.grid), dim3(kWG), 0, stream, ga);
+            if (M) {
+                launch_apply<APPLY_LANCZOS>(M, La.grid, aa, stream);
+                finish<FIN_LZ_BETA>(fl, La.grid, stream);
+            } else {
+                finish<FIN_LZ_BETA>(fl, Lg.grid, stream);
+            }
+            HIP_TRY(hipGetLastError());
+            if ((j & 31) == 31 && j + 1 < steps) {
+                HIP_TRY(hipMemcpyAsync(&h, ls, sizeof(h), hipMemcpyDeviceToHost, stream));
+                HIP_TRY(hipStreamSynchronize(stream));
+                if (h.done) break;
+            }
         }
     }
     hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(64), 0, stream, ls, al, be);

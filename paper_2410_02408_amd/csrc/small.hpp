@@ -16,6 +16,8 @@
 // iteration.
 #pragma once
 
+#include <type_traits>
+
 #include "blocks.hpp"
 #include "common.hpp"
 #include "finish.hpp"
@@ -72,24 +74,26 @@ constexpr int kSmallR = kSmallMaxRows / kSmallWG;
 // and written by the one lane that owns it in its packet); this thread's
 // share of r^T z and r^T r.
 template <int G, typename TS>
-__device__ __forceinline__ void small_apply(const SmallArgs &a, double *w, double &rz, double &rr) {
+__device__ __forceinline__ void small_apply(int n, int nblocks, int num_packets, int uniform_nb,
+                                            const int32_t *off, const void *tiles_, double *w, double &rz,
+                                            double &rr) {
     constexpr int P = 64 / G, E = packet_elems(G);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane / G, i = lane % G;
-    const TS *tiles = static_cast<const TS *>(a.tiles);
-    for (int pk = wave; pk < a.num_packets; pk += kSmallWaves) {
+    const TS *tiles = static_cast<const TS *>(tiles_);
+    for (int pk = wave; pk < num_packets; pk += kSmallWaves) {
         const int t = pk * P + g;
         int s, nn;
-        if (a.uniform_nb > 0) {
-            s = t * a.uniform_nb;
-            nn = max(0, min(a.uniform_nb, a.n - s));
+        if (uniform_nb > 0) {
+            s = t * uniform_nb;
+            nn = max(0, min(uniform_nb, n - s));
         } else {
-            const int tc = min(t, a.nblocks - 1);
-            s = t < a.nblocks ? a.off[tc] : 0;
-            nn = t < a.nblocks ? a.off[tc + 1] - a.off[tc] : 0;
+            const int tc = min(t, nblocks - 1);
+            s = t < nblocks ? off[tc] : 0;
+            nn = t < nblocks ? off[tc + 1] - off[tc] : 0;
         }
         const bool act = i < nn;
-        const int rc = min(s + i, a.n - 1);
+        const int rc = min(s + i, n - 1);
         TS dv[G / 2 + 1];
         packet_load<G, TS>(tiles + (size_t)pk * E, lane, g, i, dv);
         const double rv = act ? w[rc] : 0.0;
@@ -176,7 +180,7 @@ __global__ __launch_bounds__(kSmallWG) void k_pcg_small(SmallArgs a) {
                 if (i < n) w[i] = r[k];
             }
             __syncthreads();   // r complete before the packets read it
-            small_apply<G, TS>(a, w, rz, rr);
+            small_apply<G, TS>(a.n, a.nblocks, a.num_packets, a.uniform_nb, a.off, a.tiles, w, rz, rr);
         } else {
 #pragma unroll
             for (int k = 0; k < kSmallR; ++k) {
@@ -302,6 +306,205 @@ __global__ __launch_bounds__(kSmallWG) void k_pcg_small(SmallArgs a) {
     if (tid == 0) {
         store_state(a.out, L);
         *a.repl_out = repl;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Lanczos with CGS2 reorthogonalisation for a small system in one workgroup:
+// the steps of the multi-launch estimate (k_spmv LANCZOS, k_gram, the
+// application, the FIN_LZ_* decisions) with workgroup barriers in place of
+// launches.  The basis (U, V) is kept in the workspace (it stays in the
+// caches); the vector the product gathers, r~ / z~ of the application and
+// the Gram coefficients are staged in LDS, each thread's rows of r, z, u_j,
+// u_{j-1} in registers.  The coefficients of up to kSmallGroupL basis vectors
+// are formed per round: every wave reduces its partial dots in LDS and the
+// waves' sums are added after one barrier.  The scalar decisions are taken
+// by thread 0 on a state in LDS that every thread then reads.
+// ---------------------------------------------------------------------------
+constexpr int kSmallGroupL = 64;
+constexpr int kSmallMaxSteps = 2048;   // the coefficients live in LDS
+
+struct LanczosSmallArgs {
+    int n;
+    const int32_t *rp, *ci;
+    const double *val;
+    int nblocks, num_packets, uniform_nb;
+    const int32_t *off;
+    const void *tiles;
+    const double *v0;
+    int steps;
+    double *U, *V;       // basis vector l at l * ld (V == U without a preconditioner)
+    size_t ld;
+    double *alpha, *beta;
+    LanczosState *ls;    // the final state (read by k_tridiag and the host)
+};
+
+template <int G, typename TS, bool HAS_M>
+__global__ __launch_bounds__(kSmallWG) void k_lanczos_small(LanczosSmallArgs a) {
+    extern __shared__ double lds[];
+    const int n = a.n, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double *vg = lds, *w = lds + n, *cf = lds + 2 * n;   // gathered vector, r~ / z~, coefficients
+    __shared__ double red[kSmallGroupL][kSmallWaves];
+    __shared__ double sred[2][kSmallWaves];
+    __shared__ LanczosState S;
+    int kb[kSmallR], ke[kSmallR];
+    double r[kSmallR], z[kSmallR], uj[kSmallR], up[kSmallR];
+#pragma unroll
+    for (int k = 0; k < kSmallR; ++k) {
+        const int i = tid + k * kSmallWG;
+        kb[k] = i < n ? a.rp[i] : 0;
+        ke[k] = i < n ? a.rp[i + 1] : 0;
+        r[k] = i < n ? a.v0[i] : 0.0;
+        z[k] = uj[k] = up[k] = 0.0;
+    }
+    if (tid == 0) {
+        S.invb = S.beta_prev = S.alpha_j = S.scale = 0.0;
+        S.theta_min = S.theta_max = S.kappa = 0.0;
+        S.j = 0;
+        S.done = 0;
+        S.status = BJP_OK;
+        S.steps_done = 0;
+        S.steps = a.steps;
+        S.pad = 0;
+    }
+    FinishArgs f{};
+    f.alpha_out = a.alpha;
+    f.beta_out = a.beta;
+    // z = M^-1 r (own rows, through w); returns this thread's share of r^T z
+    auto precondition = [&]() -> double {
+        double rz = 0.0;
+        if constexpr (HAS_M) {
+#pragma unroll
+            for (int k = 0; k < kSmallR; ++k) {
+                const int i = tid + k * kSmallWG;
+                if (i < n) w[i] = r[k];
+            }
+            __syncthreads();
+            double rr = 0.0;
+            small_apply<G, TS>(a.n, a.nblocks, a.num_packets, a.uniform_nb, a.off, a.tiles, w, rz, rr);
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < kSmallR; ++k) {
+                const int i = tid + k * kSmallWG;
+                z[k] = i < n ? w[i] : 0.0;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kSmallR; ++k) {
+                z[k] = r[k];
+                rz += r[k] * r[k];
+            }
+        }
+        return rz;
+    };
+    // thread 0 takes decision OP on the totals; every thread then reads S
+    auto decide = [&](auto op_tag, double (&v)[1]) {
+        constexpr int OP = decltype(op_tag)::value;
+        small_sum<1>(v, sred);
+        if (tid == 0) finish_decide<OP>(f, nullptr, &S, v);
+        __syncthreads();
+    };
+    {
+        double v[1] = {precondition()};
+        decide(std::integral_constant<int, FIN_LZ_START>{}, v);
+    }
+    while (!S.done) {
+        const int j = S.j;
+        const double invb = S.invb;
+        // v_j = z~ / beta, u_j = r~ / beta: stored, and v_j staged for the product
+#pragma unroll
+        for (int k = 0; k < kSmallR; ++k) {
+            const int i = tid + k * kSmallWG;
+            up[k] = uj[k];
+            uj[k] = r[k] * invb;
+            if (i < n) {
+                const double vj = z[k] * invb;
+                a.V[(size_t)j * a.ld + i] = vj;
+                if (HAS_M) a.U[(size_t)j * a.ld + i] = uj[k];
+                vg[i] = vj;
+            }
+        }
+        __syncthreads();
+        // w = A v_j, alpha_j = v_j^T w; r~ = w - alpha_j u_j - beta_{j-1} u_{j-1}
+        {
+            double v[1] = {0.0};
+#pragma unroll
+            for (int k = 0; k < kSmallR; ++k) {
+                if (tid + k * kSmallWG < n) {
+                    double acc = 0.0;
+                    for (int e = kb[k]; e < ke[k]; ++e) acc += a.val[e] * vg[a.ci[e]];
+                    r[k] = acc;   // w, turned into r~ below
+                    v[0] += vg[tid + k * kSmallWG] * acc;
+                }
+            }
+            decide(std::integral_constant<int, FIN_LZ_ALPHA>{}, v);
+        }
+        if (S.done) break;
+        const double al = S.alpha_j, bp = S.beta_prev;
+#pragma unroll
+        for (int k = 0; k < kSmallR; ++k) {
+            r[k] -= al * uj[k];
+            if (j > 0) r[k] -= bp * up[k];
+        }
+        // classical Gram-Schmidt, twice: c_l = v_l^T r~ (l <= j), r~ -= sum_l c_l u_l
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int g0 = 0; g0 <= j; g0 += kSmallGroupL) {
+                const int g1 = min(g0 + kSmallGroupL, j + 1);
+                for (int l0 = g0; l0 < g1; l0 += 4) {
+                    double sv[4];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int l = min(l0 + t, j);
+                        double s = 0.0;
+#pragma unroll
+                        for (int k = 0; k < kSmallR; ++k) {
+                            const int i = tid + k * kSmallWG;
+                            if (i < n) s += a.V[(size_t)l * a.ld + i] * r[k];
+                        }
+                        sv[t] = s;
+                    }
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const double tsum = wave_sum(sv[t]);
+                        if (lane == 0) red[l0 - g0 + t][wave] = tsum;
+                    }
+                }
+                __syncthreads();
+                if (tid < g1 - g0) {
+                    double s = 0.0;
+                    for (int wv = 0; wv < kSmallWaves; ++wv) s += red[tid][wv];
+                    cf[g0 + tid] = s;
+                }
+                __syncthreads();
+            }
+            for (int l = 0; l <= j; ++l) {
+                const double cl = cf[l];
+#pragma unroll
+                for (int k = 0; k < kSmallR; ++k) {
+                    const int i = tid + k * kSmallWG;
+                    if (i < n) r[k] -= cl * a.U[(size_t)l * a.ld + i];
+                }
+            }
+            __syncthreads();   // cf is overwritten by the next pass
+        }
+        // z~ = M^-1 r~, beta_j = sqrt(r~^T z~)
+        double v[1] = {precondition()};
+        decide(std::integral_constant<int, FIN_LZ_BETA>{}, v);
+    }
+    if (tid == 0) {
+        a.ls->invb = S.invb;
+        a.ls->beta_prev = S.beta_prev;
+        a.ls->alpha_j = S.alpha_j;
+        a.ls->scale = S.scale;
+        a.ls->theta_min = S.theta_min;
+        a.ls->theta_max = S.theta_max;
+        a.ls->kappa = S.kappa;
+        a.ls->j = S.j;
+        a.ls->done = S.done;
+        a.ls->status = S.status;
+        a.ls->steps_done = S.steps_done;
+        a.ls->steps = S.steps;
+        a.ls->pad = 0;
     }
 }
 

@@ -352,14 +352,53 @@ def test_kappa_single_block_and_breakdown(gpu):
     assert k.status == "EBREAKDOWN"
 
 
-def test_kappa_many_steps_tiles(gpu, orc):
-    """More than one LDS tile of Gram coefficients (j > 256)."""
-    A = w.random_spd(400, np.random.default_rng(11), shift=0.3)
+@pytest.mark.parametrize("n", [400, 2100], ids=["one-workgroup", "multi-launch"])
+def test_kappa_many_steps_tiles(gpu, orc, n):
+    """More than one group of Gram coefficients (j > 256): 400 rows take the
+    one-workgroup estimate, 2100 the multi-launch one."""
+    A = w.random_spd(n, np.random.default_rng(11), shift=0.3)
     Ad = dev(A)
-    k = gpu.kappa_estimate(Ad, w.rhs(400, 21), 300)
-    ko = orc.kappa(A, w.rhs(400, 21), 300)
+    k = gpu.kappa_estimate(Ad, w.rhs(n, 21), 300)
+    ko = orc.kappa(A, w.rhs(n, 21), 300)
     assert k.steps == ko.steps
     assert abs(k.kappa - ko.kappa) <= 1e-6 * ko.kappa
+
+
+KAPPA_SMALL = [("poisson2d_32 fp32-stored", lambda: (w.poisson2d(32), w.rhs(1024, 0)), 16, "fp32", 100),
+               ("random_spd_777 explicit blocks", lambda: (w.random_spd(777, np.random.default_rng(81)),
+                                                           w.rhs(777, 85)), 0, "explicit", 120),
+               ("random_spd_2048/64", lambda: (w.random_spd(2048, np.random.default_rng(79)), w.rhs(2048, 86)),
+                64, None, 150),
+               ("diffusion3d_12/8", lambda: (w.diffusion3d(12, 1.5, 1), w.rhs(1728, 1)), 8, None, 100),
+               ("diffusion3d_12 plain", lambda: (w.diffusion3d(12, 1.5, 1), w.rhs(1728, 1)), 0, None, 100)]
+
+
+@pytest.mark.parametrize("name,make,nb,kind,steps", KAPPA_SMALL, ids=[c[0] for c in KAPPA_SMALL])
+def test_kappa_one_workgroup_matches_oracle(gpu, orc, name, make, nb, kind, steps):
+    """The one-workgroup estimate (systems of at most 2048 rows) against the
+    oracle's CGS2 Lanczos: equal step counts, kappa within 1e-6, the
+    tridiagonal within 1e-8."""
+    print(f"case {name}", flush=True)
+    A, b = make()
+    Ad = dev(A)
+    if kind == "explicit":
+        sizes = np.random.default_rng(83).integers(1, 65, size=A.n)
+        off = np.concatenate([[0], np.cumsum(sizes)])
+        off = off[off < A.n].tolist() + [A.n]
+        Md, Mo = gpu.precondition(Ad, offsets=off), orc.Precond(A, off)
+    elif nb:
+        Md = gpu.precondition(Ad, block_size=nb, precision="fp32" if kind == "fp32" else "fp64")
+        Mo = orc.Precond.uniform(A, nb)
+    else:
+        Md = Mo = None
+    k = gpu.kappa_estimate(Ad, b, steps, Md)
+    ko = orc.kappa(A, b, steps, Mo)
+    print(f"  gpu {k.kappa:.12g} ({k.steps} steps) oracle {ko.kappa:.12g} ({ko.steps})", flush=True)
+    assert k.status == ko.status == "OK" and k.steps == ko.steps
+    tol = 1e-5 if kind == "fp32" else 1e-6
+    assert abs(k.kappa - ko.kappa) <= tol * ko.kappa
+    if kind != "fp32":
+        np.testing.assert_allclose(k.alpha, ko.alpha, rtol=1e-8, atol=1e-12)
 
 
 @BOTH_SOLVERS
