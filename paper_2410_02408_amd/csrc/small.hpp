@@ -49,8 +49,8 @@ struct SmallArgs {
 // Totals of NQ per-thread values over the workgroup, in a fixed order; every
 // thread receives them.  Ends with a barrier, so `red` can be reused and every
 // store made before the call is visible to the whole workgroup after it.
-template <int NQ>
-__device__ __forceinline__ void small_sum(double (&v)[NQ], double (*red)[kSmallWaves]) {
+template <int NQ, int WAVES = kSmallWaves>
+__device__ __forceinline__ void small_sum(double (&v)[NQ], double (*red)[WAVES]) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
@@ -61,7 +61,7 @@ __device__ __forceinline__ void small_sum(double (&v)[NQ], double (*red)[kSmallW
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         double t = 0.0;
-        for (int w = 0; w < kSmallWaves; ++w) t += red[q][w];
+        for (int w = 0; w < WAVES; ++w) t += red[q][w];
         v[q] = t;
     }
     __syncthreads();
@@ -73,7 +73,7 @@ constexpr int kSmallR = kSmallMaxRows / kSmallWG;
 // z = M^-1 r over every packet, in place in w (r in, z out; each row is read
 // and written by the one lane that owns it in its packet); this thread's
 // share of r^T z and r^T r.
-template <int G, typename TS>
+template <int G, typename TS, int WAVES = kSmallWaves>
 __device__ __forceinline__ void small_apply(int n, int nblocks, int num_packets, int uniform_nb,
                                             const int32_t *off, const void *tiles_, double *w, double &rz,
                                             double &rr) {
@@ -81,7 +81,7 @@ __device__ __forceinline__ void small_apply(int n, int nblocks, int num_packets,
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane / G, i = lane % G;
     const TS *tiles = static_cast<const TS *>(tiles_);
-    for (int pk = wave; pk < num_packets; pk += kSmallWaves) {
+    for (int pk = wave; pk < num_packets; pk += WAVES) {
         const int t = pk * P + g;
         int s, nn;
         if (uniform_nb > 0) {
@@ -313,16 +313,55 @@ __global__ __launch_bounds__(kSmallWG) void k_pcg_small(SmallArgs a) {
 // Lanczos with CGS2 reorthogonalisation for a small system in one workgroup:
 // the steps of the multi-launch estimate (k_spmv LANCZOS, k_gram, the
 // application, the FIN_LZ_* decisions) with workgroup barriers in place of
-// launches.  The basis (U, V) is kept in the workspace (it stays in the
-// caches); the vector the product gathers, r~ / z~ of the application and
-// the Gram coefficients are staged in LDS, each thread's rows of r, z, u_j,
-// u_{j-1} in registers.  The coefficients of up to kSmallGroupL basis vectors
-// are formed per round: every wave reduces its partial dots in LDS and the
-// waves' sums are added after one barrier.  The scalar decisions are taken
-// by thread 0 on a state in LDS that every thread then reads.
+// launches.  The basis (U, V) is kept in the workspace, where it stays in the
+// caches; a step streams it four times.  The two halves of a Gram pass are
+// split differently:
+//   coefficients c_l = v_l^T r~: a wave computes whole coefficients (wave w
+//     takes l = w*CP .. w*CP+CP-1, then every kSmallWaves*CP-th group), each
+//     lane holding rows lane, lane+64, ... of r~ in registers (staged once
+//     per pass through LDS), so each coefficient takes one wave reduction
+//     and no exchange between waves;
+//   r~ -= sum_l c_l u_l: by rows, each thread its own, l in order, with the
+//     loads of kLzUnroll basis vectors in flight (deeper rounds measured no
+//     faster: one workgroup streams the basis from L2 at about 60 GB/s
+//     either way, which bounds the estimate at 1024 rows and 100 steps,
+//     165 MB of basis reads, near 2.7 ms).
+// The vector the product gathers, r~ / z~ of the application and the
+// coefficients are staged in LDS, each thread's rows of r, z, u_j, u_{j-1}
+// in registers.  The scalar decisions are taken by thread 0 on a state in LDS
+// that every thread then reads.
 // ---------------------------------------------------------------------------
-constexpr int kSmallGroupL = 64;
-constexpr int kSmallMaxSteps = 2048;   // the coefficients live in LDS
+constexpr int kLzUnroll = 8;                  // basis vectors per round of the update loop
+constexpr int kLzDotLoads = 32;               // basis loads in flight per lane in the dot loop
+constexpr int kSmallMaxSteps = 2048;          // the coefficients live in LDS
+
+// Wave totals of UN per-lane values at once (UN a power of two, at most 64).
+// In each of the first log2(UN) butterfly stages a lane keeps half of its
+// values and adds its partner's copies of them, handing the other half to
+// the partner; the remaining stages add single values.  Lane L ends with the
+// total of value L / (64 / UN).  Fixed order, so deterministic.
+template <int H, int OFF>
+__device__ __forceinline__ void butterfly_stage(double *s, int lane) {
+    if constexpr (H >= 1) {
+        const bool hi = (lane & OFF) != 0;
+#pragma unroll
+        for (int k = 0; k < H; ++k) {
+            const double keep = hi ? s[H + k] : s[k];
+            const double give = hi ? s[k] : s[H + k];
+            s[k] = keep + __shfl_xor(give, OFF, 64);
+        }
+        butterfly_stage<H / 2, OFF / 2>(s, lane);
+    }
+}
+template <int UN>
+__device__ __forceinline__ double wave_sums_transposed(double (&s)[UN]) {
+    const int lane = threadIdx.x & 63;
+    butterfly_stage<UN / 2, 32>(s, lane);
+    double v = s[0];
+#pragma unroll
+    for (int off = 32 / UN; off >= 1; off /= 2) v += __shfl_xor(v, off, 64);
+    return v;
+}
 
 struct LanczosSmallArgs {
     int n;
@@ -341,22 +380,95 @@ struct LanczosSmallArgs {
 
 template <int G, typename TS, bool HAS_M>
 __global__ __launch_bounds__(kSmallWG) void k_lanczos_small(LanczosSmallArgs a) {
+    constexpr int WG = kSmallWG, W = kSmallWaves, R = kSmallR;
     extern __shared__ double lds[];
     const int n = a.n, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    double *vg = lds, *w = lds + n, *cf = lds + 2 * n;   // gathered vector, r~ / z~, coefficients
-    __shared__ double red[kSmallGroupL][kSmallWaves];
-    __shared__ double sred[2][kSmallWaves];
+    double *vg = lds, *w = lds + n, *cf = lds + 2 * n;   // gathered vector / staged r~, z~, coefficients
+    __shared__ double sred[1][W];
     __shared__ LanczosState S;
-    int kb[kSmallR], ke[kSmallR];
-    double r[kSmallR], z[kSmallR], uj[kSmallR], up[kSmallR];
+    int kb[R], ke[R];
+    double r[R], z[R], uj[R], up[R];
 #pragma unroll
-    for (int k = 0; k < kSmallR; ++k) {
-        const int i = tid + k * kSmallWG;
+    for (int k = 0; k < R; ++k) {
+        const int i = tid + k * WG;
         kb[k] = i < n ? a.rp[i] : 0;
         ke[k] = i < n ? a.rp[i + 1] : 0;
         r[k] = i < n ? a.v0[i] : 0.0;
         z[k] = uj[k] = up[k] = 0.0;
     }
+    // clamped row index of slot k (rows past n are masked by value)
+    auto row_of = [&](int k) { return min(tid + k * WG, n - 1); };
+    // a wave whose upper half of slots holds no row below n skips their loads
+    // in the update loop (a wave-uniform branch)
+    const bool half_live = (R / 2) * WG + __builtin_amdgcn_readfirstlane(wave) * 64 >= n;
+    // c_l = v_l^T r~ for every l <= j, r~ staged in vg; NM = 64-row chunks per
+    // lane, held in registers up to 16 of them (read from LDS beyond that)
+    auto gram_dots = [&](auto nm_tag, int j) {
+        constexpr int NM = decltype(nm_tag)::value;
+        constexpr int CP = kLzDotLoads / NM > 1 ? kLzDotLoads / NM : 1;   // coefficients per round
+        constexpr bool IN_REGS = NM <= 16;
+        double rg[IN_REGS ? NM : 1];
+        auto rt = [&](int m) {
+            const int i = lane + 64 * m;
+            return i < n ? vg[i] : 0.0;
+        };
+        if constexpr (IN_REGS) {
+#pragma unroll
+            for (int m = 0; m < NM; ++m) rg[m] = rt(m);
+        }
+        // rows in halves of at most 16 chunks per lane when r~ is read from LDS
+        constexpr int MH = IN_REGS ? NM : 16;
+        for (int l0 = wave * CP; l0 <= j; l0 += W * CP) {
+            double sv[CP];
+#pragma unroll
+            for (int c = 0; c < CP; ++c) sv[c] = 0.0;
+#pragma unroll 1
+            for (int m0 = 0; m0 < NM; m0 += MH) {
+                double bv[CP][MH];
+#pragma unroll
+                for (int c = 0; c < CP; ++c) {
+                    const double *vl = a.V + (size_t)min(l0 + c, j) * a.ld;
+#pragma unroll
+                    for (int m = 0; m < MH; ++m) bv[c][m] = vl[min(lane + 64 * (m0 + m), n - 1)];
+                }
+#pragma unroll
+                for (int c = 0; c < CP; ++c)
+#pragma unroll
+                    for (int m = 0; m < MH; ++m)
+                        sv[c] += bv[c][m] * (IN_REGS ? rg[IN_REGS ? m : 0] : rt(m0 + m));
+            }
+            const double tot = wave_sums_transposed<CP>(sv);
+            const int c = lane / (64 / CP);
+            if ((lane & (64 / CP - 1)) == 0 && l0 + c <= j) cf[l0 + c] = tot;
+        }
+    };
+    // r~ -= sum_{l <= j} c_l u_l over this thread's rows, l in order
+    auto gram_axpy = [&](auto rl_tag, int j) {
+        constexpr int RL = decltype(rl_tag)::value;
+        constexpr int UN = kLzUnroll;
+        int l = 0;
+        for (; l + UN <= j + 1; l += UN) {
+            double bu[UN][RL];
+#pragma unroll
+            for (int t = 0; t < UN; ++t) {
+                const double *ul = a.U + (size_t)(l + t) * a.ld;
+#pragma unroll
+                for (int k = 0; k < RL; ++k) bu[t][k] = ul[row_of(k)];
+            }
+#pragma unroll
+            for (int t = 0; t < UN; ++t) {
+                const double cl = cf[l + t];
+#pragma unroll
+                for (int k = 0; k < RL; ++k) r[k] -= cl * bu[t][k];
+            }
+        }
+        for (; l <= j; ++l) {
+            const double cl = cf[l];
+            const double *ul = a.U + (size_t)l * a.ld;
+#pragma unroll
+            for (int k = 0; k < RL; ++k) r[k] -= cl * ul[row_of(k)];
+        }
+    };
     if (tid == 0) {
         S.invb = S.beta_prev = S.alpha_j = S.scale = 0.0;
         S.theta_min = S.theta_max = S.kappa = 0.0;
@@ -375,8 +487,8 @@ __global__ __launch_bounds__(kSmallWG) void k_lanczos_small(LanczosSmallArgs a) 
         double rz = 0.0;
         if constexpr (HAS_M) {
 #pragma unroll
-            for (int k = 0; k < kSmallR; ++k) {
-                const int i = tid + k * kSmallWG;
+            for (int k = 0; k < R; ++k) {
+                const int i = tid + k * WG;
                 if (i < n) w[i] = r[k];
             }
             __syncthreads();
@@ -384,13 +496,13 @@ __global__ __launch_bounds__(kSmallWG) void k_lanczos_small(LanczosSmallArgs a) 
             small_apply<G, TS>(a.n, a.nblocks, a.num_packets, a.uniform_nb, a.off, a.tiles, w, rz, rr);
             __syncthreads();
 #pragma unroll
-            for (int k = 0; k < kSmallR; ++k) {
-                const int i = tid + k * kSmallWG;
+            for (int k = 0; k < R; ++k) {
+                const int i = tid + k * WG;
                 z[k] = i < n ? w[i] : 0.0;
             }
         } else {
 #pragma unroll
-            for (int k = 0; k < kSmallR; ++k) {
+            for (int k = 0; k < R; ++k) {
                 z[k] = r[k];
                 rz += r[k] * r[k];
             }
@@ -413,8 +525,8 @@ __global__ __launch_bounds__(kSmallWG) void k_lanczos_small(LanczosSmallArgs a) 
         const double invb = S.invb;
         // v_j = z~ / beta, u_j = r~ / beta: stored, and v_j staged for the product
 #pragma unroll
-        for (int k = 0; k < kSmallR; ++k) {
-            const int i = tid + k * kSmallWG;
+        for (int k = 0; k < R; ++k) {
+            const int i = tid + k * WG;
             up[k] = uj[k];
             uj[k] = r[k] * invb;
             if (i < n) {
@@ -429,12 +541,12 @@ __global__ __launch_bounds__(kSmallWG) void k_lanczos_small(LanczosSmallArgs a) 
         {
             double v[1] = {0.0};
 #pragma unroll
-            for (int k = 0; k < kSmallR; ++k) {
-                if (tid + k * kSmallWG < n) {
+            for (int k = 0; k < R; ++k) {
+                if (tid + k * WG < n) {
                     double acc = 0.0;
                     for (int e = kb[k]; e < ke[k]; ++e) acc += a.val[e] * vg[a.ci[e]];
                     r[k] = acc;   // w, turned into r~ below
-                    v[0] += vg[tid + k * kSmallWG] * acc;
+                    v[0] += vg[tid + k * WG] * acc;
                 }
             }
             decide(std::integral_constant<int, FIN_LZ_ALPHA>{}, v);
@@ -442,51 +554,37 @@ __global__ __launch_bounds__(kSmallWG) void k_lanczos_small(LanczosSmallArgs a) 
         if (S.done) break;
         const double al = S.alpha_j, bp = S.beta_prev;
 #pragma unroll
-        for (int k = 0; k < kSmallR; ++k) {
+        for (int k = 0; k < R; ++k) {
             r[k] -= al * uj[k];
             if (j > 0) r[k] -= bp * up[k];
         }
         // classical Gram-Schmidt, twice: c_l = v_l^T r~ (l <= j), r~ -= sum_l c_l u_l
         for (int pass = 0; pass < 2; ++pass) {
-            for (int g0 = 0; g0 <= j; g0 += kSmallGroupL) {
-                const int g1 = min(g0 + kSmallGroupL, j + 1);
-                for (int l0 = g0; l0 < g1; l0 += 4) {
-                    double sv[4];
+            // r~ staged in vg (free since the product); every gather of v_j
+            // is done, as a decision's barrier has passed since
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const int l = min(l0 + t, j);
-                        double s = 0.0;
-#pragma unroll
-                        for (int k = 0; k < kSmallR; ++k) {
-                            const int i = tid + k * kSmallWG;
-                            if (i < n) s += a.V[(size_t)l * a.ld + i] * r[k];
-                        }
-                        sv[t] = s;
-                    }
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const double tsum = wave_sum(sv[t]);
-                        if (lane == 0) red[l0 - g0 + t][wave] = tsum;
-                    }
-                }
-                __syncthreads();
-                if (tid < g1 - g0) {
-                    double s = 0.0;
-                    for (int wv = 0; wv < kSmallWaves; ++wv) s += red[tid][wv];
-                    cf[g0 + tid] = s;
-                }
-                __syncthreads();
+            for (int k = 0; k < R; ++k) {
+                const int i = tid + k * WG;
+                if (i < n) vg[i] = r[k];
             }
-            for (int l = 0; l <= j; ++l) {
-                const double cl = cf[l];
-#pragma unroll
-                for (int k = 0; k < kSmallR; ++k) {
-                    const int i = tid + k * kSmallWG;
-                    if (i < n) r[k] -= cl * a.U[(size_t)l * a.ld + i];
-                }
-            }
-            __syncthreads();   // cf is overwritten by the next pass
+            __syncthreads();
+            if (n <= 256)
+                gram_dots(std::integral_constant<int, 4>{}, j);
+            else if (n <= 512)
+                gram_dots(std::integral_constant<int, 8>{}, j);
+            else if (n <= 1024)
+                gram_dots(std::integral_constant<int, 16>{}, j);
+            else
+                gram_dots(std::integral_constant<int, 32>{}, j);
+            __syncthreads();   // cf complete; vg read by every wave
+            if (half_live)
+                gram_axpy(std::integral_constant<int, R / 2>{}, j);
+            else
+                gram_axpy(std::integral_constant<int, R>{}, j);
         }
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if (tid + k * WG >= n) r[k] = 0.0;
         // z~ = M^-1 r~, beta_j = sqrt(r~^T z~)
         double v[1] = {precondition()};
         decide(std::integral_constant<int, FIN_LZ_BETA>{}, v);

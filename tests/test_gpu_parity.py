@@ -370,7 +370,9 @@ KAPPA_SMALL = [("poisson2d_32 fp32-stored", lambda: (w.poisson2d(32), w.rhs(1024
                ("random_spd_2048/64", lambda: (w.random_spd(2048, np.random.default_rng(79)), w.rhs(2048, 86)),
                 64, None, 150),
                ("diffusion3d_12/8", lambda: (w.diffusion3d(12, 1.5, 1), w.rhs(1728, 1)), 8, None, 100),
-               ("diffusion3d_12 plain", lambda: (w.diffusion3d(12, 1.5, 1), w.rhs(1728, 1)), 0, None, 100)]
+               ("diffusion3d_12 plain", lambda: (w.diffusion3d(12, 1.5, 1), w.rhs(1728, 1)), 0, None, 100),
+               ("random_spd_2048 plain", lambda: (w.random_spd(2048, np.random.default_rng(87), shift=0.2),
+                                                  w.rhs(2048, 88)), 0, None, 130)]
 
 
 @pytest.mark.parametrize("name,make,nb,kind,steps", KAPPA_SMALL, ids=[c[0] for c in KAPPA_SMALL])
