@@ -264,26 +264,64 @@ void launch_apply(const bjp_precond_t *M, int grid, const ApplyArgs &a, hipStrea
     else launch_apply_t<double, MODE>(M->group, grid, a, s);
 }
 
-// The one-workgroup solver keeps two n-vectors in LDS (16 n bytes).
-template <typename TS>
-void launch_small_t(int G, const SmallArgs &a, hipStream_t s) {
-    const size_t lds = 2 * sizeof(double) * (size_t)a.n;
+// Launches a one-workgroup kernel with `lds` bytes of dynamic LDS (above
+// 64 KB the kernel is first allowed that much).
+template <typename K, typename A>
+void launch_one_workgroup(K kernel, size_t lds, hipStream_t s, const A &a) {
+    if (lds > 65536)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+    hipLaunchKernelGGL(kernel, dim3(1), dim3(kSmallWG), lds, s, a);
+}
+
+template <typename TS, int RES>
+void launch_small_g(int G, const SmallArgs &a, size_t lds, hipStream_t s) {
     switch (G) {
-        case 1: hipLaunchKernelGGL((k_pcg_small<1, TS, true>), dim3(1), dim3(kSmallWG), lds, s, a); break;
-        case 2: hipLaunchKernelGGL((k_pcg_small<2, TS, true>), dim3(1), dim3(kSmallWG), lds, s, a); break;
-        case 4: hipLaunchKernelGGL((k_pcg_small<4, TS, true>), dim3(1), dim3(kSmallWG), lds, s, a); break;
-        case 8: hipLaunchKernelGGL((k_pcg_small<8, TS, true>), dim3(1), dim3(kSmallWG), lds, s, a); break;
-        case 16: hipLaunchKernelGGL((k_pcg_small<16, TS, true>), dim3(1), dim3(kSmallWG), lds, s, a); break;
-        case 32: hipLaunchKernelGGL((k_pcg_small<32, TS, true>), dim3(1), dim3(kSmallWG), lds, s, a); break;
-        default: hipLaunchKernelGGL((k_pcg_small<64, TS, true>), dim3(1), dim3(kSmallWG), lds, s, a); break;
+        case 1: launch_one_workgroup(k_pcg_small<1, TS, true, RES>, lds, s, a); break;
+        case 2: launch_one_workgroup(k_pcg_small<2, TS, true, RES>, lds, s, a); break;
+        case 4: launch_one_workgroup(k_pcg_small<4, TS, true, RES>, lds, s, a); break;
+        case 8: launch_one_workgroup(k_pcg_small<8, TS, true, RES>, lds, s, a); break;
+        case 16: launch_one_workgroup(k_pcg_small<16, TS, true, RES>, lds, s, a); break;
+        case 32: launch_one_workgroup(k_pcg_small<32, TS, true, RES>, lds, s, a); break;
+        default: launch_one_workgroup(k_pcg_small<64, TS, true, RES>, lds, s, a); break;
     }
 }
 
-void launch_small(const bjp_precond_t *M, const SmallArgs &a, hipStream_t s) {
-    const size_t lds = 2 * sizeof(double) * (size_t)a.n;
-    if (!M) hipLaunchKernelGGL((k_pcg_small<1, double, false>), dim3(1), dim3(kSmallWG), lds, s, a);
-    else if (M->precision == BJP_FP32_STORE) launch_small_t<float>(M->group, a, s);
-    else launch_small_t<double>(M->group, a, s);
+template <typename TS>
+void launch_small_t(int G, int res, const SmallArgs &a, size_t lds, hipStream_t s) {
+    switch (res) {
+        case 0: launch_small_g<TS, 0>(G, a, lds, s); break;
+        case kResTiles: launch_small_g<TS, kResTiles>(G, a, lds, s); break;
+        case kResCsr: launch_small_g<TS, kResCsr>(G, a, lds, s); break;
+        default: launch_small_g<TS, kResTiles | kResCsr>(G, a, lds, s); break;
+    }
+}
+
+// What of the inverse packets and the CSR the one-workgroup solver keeps in
+// LDS beside its two vectors: the packets if they fit, then the CSR if it
+// fits too.
+int small_residency(const SmallArgs &a, bool has_m) {
+    const size_t vec = 2 * sizeof(double) * (size_t)a.n;
+    int res = 0;
+    if (has_m && vec + small_stage_bytes(kResTiles, a.nnz, a.tiles_bytes) <= kSmallLdsBytes) res |= kResTiles;
+    if (vec + small_stage_bytes(res | kResCsr, a.nnz, a.tiles_bytes) <= kSmallLdsBytes) res |= kResCsr;
+    return res;
+}
+
+void launch_small(const bjp_precond_t *M, SmallArgs a, hipStream_t s) {
+    a.tiles_bytes = M ? (int)((size_t)M->num_packets * packet_elems(M->group) *
+                              (M->precision == BJP_FP32_STORE ? sizeof(float) : sizeof(double)))
+                      : 0;
+    const int res = small_residency(a, M != nullptr);
+    const size_t lds = 2 * sizeof(double) * (size_t)a.n + small_stage_bytes(res, a.nnz, a.tiles_bytes);
+    if (!M) {
+        if (res & kResCsr) launch_one_workgroup(k_pcg_small<1, double, false, kResCsr>, lds, s, a);
+        else launch_one_workgroup(k_pcg_small<1, double, false, 0>, lds, s, a);
+    } else if (M->precision == BJP_FP32_STORE) {
+        launch_small_t<float>(M->group, res, a, lds, s);
+    } else {
+        launch_small_t<double>(M->group, res, a, lds, s);
+    }
 }
 
 // The one-workgroup Lanczos keeps two n-vectors and the step's Gram
@@ -840,6 +878,7 @@ int pcg_solve_impl(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, 
         !o.timing) {
         SmallArgs sm{};
         sm.n = n;
+        sm.nnz = (int)A->nnz;
         sm.rp = A->row_ptr;
         sm.ci = A->col_idx;
         sm.val = A->val;

@@ -12,8 +12,10 @@
 // the block-inverse application runs packet by packet on the waves (wave w
 // takes packets w, w + kSmallWaves, ...) on r staged in LDS.  Every total is
 // a fixed-order workgroup reduction, so the solve is deterministic.  Only the
-// matrix and the block inverses are read from memory (from the caches) in an
-// iteration.
+// matrix and the block inverses are read in an iteration, and one workgroup
+// streams them from L2 at only about 60 GB/s, so whatever of them fits in
+// LDS beside the vectors (the inverse packets first, then the CSR values and
+// columns; 160 KB per workgroup on gfx950) is copied there once per solve.
 #pragma once
 
 #include <type_traits>
@@ -28,9 +30,15 @@ constexpr int kSmallWG = 512;
 constexpr int kSmallWaves = kSmallWG / 64;
 constexpr int kSmallMaxRows = 4 * kSmallWG;   // at most 4 rows per thread
 constexpr int kSmallMaxMeanRow = 32;          // longer rows take the multi-launch products
+// dynamic LDS a one-workgroup kernel may take (gfx950: 160 KB per workgroup,
+// less what the kernels declare statically)
+constexpr size_t kSmallLdsBytes = 160 * 1024 - 2048;
+// what a one-workgroup kernel keeps in LDS besides its vectors (bits)
+constexpr int kResTiles = 1, kResCsr = 2;
 
 struct SmallArgs {
-    int n;
+    int n, nnz;
+    int tiles_bytes;         // bytes of the inverse packets (copied to LDS with kResTiles)
     const int32_t *rp, *ci;
     const double *val;
     const double *b;
@@ -112,12 +120,47 @@ __device__ __forceinline__ void small_apply(int n, int nblocks, int num_packets,
 // doubles each; every thread keeps x, r and p of its own rows in registers
 // (q = A p of its rows goes to w, which is free until the next application)
 // and the extents of its rows' CSR entries.
-template <int G, typename TS, bool HAS_M>
+// Copies what RES names to LDS after the two vectors; the pointers then
+// refer to the copies.  Ends with a barrier.
+template <int RES>
+__device__ __forceinline__ void small_stage(double *lds, int n, int nnz, int tiles_bytes, const void *&tiles,
+                                            const double *&val, const int32_t *&ci) {
+    char *rest = reinterpret_cast<char *>(lds + 2 * (size_t)n);
+    if constexpr ((RES & kResTiles) != 0) {
+        const uint4 *src = static_cast<const uint4 *>(tiles);
+        uint4 *dst = reinterpret_cast<uint4 *>(rest);
+        for (int q = threadIdx.x; q < tiles_bytes / 16; q += kSmallWG) dst[q] = src[q];
+        tiles = rest;
+        rest += tiles_bytes;
+    }
+    if constexpr ((RES & kResCsr) != 0) {
+        double *lv = reinterpret_cast<double *>(rest);
+        int32_t *lc = reinterpret_cast<int32_t *>(lv + nnz);
+        for (int e = threadIdx.x; e < nnz; e += kSmallWG) {
+            lv[e] = val[e];
+            lc[e] = ci[e];
+        }
+        val = lv;
+        ci = lc;
+    }
+    __syncthreads();
+}
+
+// LDS bytes of what RES names (the vectors not included)
+__host__ __device__ constexpr size_t small_stage_bytes(int res, int nnz, int tiles_bytes) {
+    return ((res & kResTiles) ? (size_t)tiles_bytes : 0) + ((res & kResCsr) ? (size_t)nnz * 12 : 0);
+}
+
+template <int G, typename TS, bool HAS_M, int RES>
 __global__ __launch_bounds__(kSmallWG) void k_pcg_small(SmallArgs a) {
     extern __shared__ double lds[];
     double *u = lds, *w = lds + a.n;
     __shared__ double red[2][kSmallWaves];
     const int tid = threadIdx.x, n = a.n;
+    const void *tiles = a.tiles;
+    const double *val = a.val;
+    const int32_t *ci = a.ci;
+    small_stage<RES>(lds, n, a.nnz, a.tiles_bytes, tiles, val, ci);
     int kb[kSmallR], ke[kSmallR];
     double x[kSmallR], r[kSmallR], p[kSmallR];
 #pragma unroll
@@ -130,7 +173,7 @@ __global__ __launch_bounds__(kSmallWG) void k_pcg_small(SmallArgs a) {
     // (A u) of this thread's row k, entries in storage order
     auto row = [&](int k) {
         double acc = 0.0;
-        for (int e = kb[k]; e < ke[k]; ++e) acc += a.val[e] * u[a.ci[e]];
+        for (int e = kb[k]; e < ke[k]; ++e) acc += val[e] * u[ci[e]];
         return acc;
     };
     PcgState L;
@@ -180,7 +223,7 @@ __global__ __launch_bounds__(kSmallWG) void k_pcg_small(SmallArgs a) {
                 if (i < n) w[i] = r[k];
             }
             __syncthreads();   // r complete before the packets read it
-            small_apply<G, TS>(a.n, a.nblocks, a.num_packets, a.uniform_nb, a.off, a.tiles, w, rz, rr);
+            small_apply<G, TS>(a.n, a.nblocks, a.num_packets, a.uniform_nb, a.off, tiles, w, rz, rr);
         } else {
 #pragma unroll
             for (int k = 0; k < kSmallR; ++k) {

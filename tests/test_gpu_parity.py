@@ -602,7 +602,14 @@ def test_duplicates_and_unsorted_columns(gpu, orc, name, make, nb, schedules):
         _pcg_parity(gpu, orc, A, b, nb, case=name, spmv_lanes=lanes)
 
 
+# What the one-workgroup solver keeps in LDS besides its vectors (160 KB in
+# all): poisson2d_32/16 the inverse packets and the CSR (FP64 and FP32),
+# poisson2d_45/8 the packets only, poisson2d_32 plain CG and the explicit
+# blocks the CSR only, the random 2048-row and 2001-row systems and
+# diffusion3d_12/64 neither.
 SMALL_CASES = [("poisson2d_32/16", lambda: w.workload("poisson2d_32"), 16, None),
+               ("poisson2d_45/8 (2025 rows, packets in LDS)", lambda: w.poisson2d(45), 8, None),
+               ("random_spd_2048 plain CG", lambda: w.random_spd(2048, np.random.default_rng(79)), 0, None),
                ("diffusion3d_12/64 (1728 rows)", lambda: w.workload("diffusion3d_12"), 64, None),
                ("random_spd_2048/64 (the largest one-workgroup size)", lambda: w.random_spd(2048, np.random.default_rng(79)), 64, None),
                ("random_spd_2001/24 (ragged last block)", lambda: w.random_spd(2001, np.random.default_rng(80)), 24, None),
