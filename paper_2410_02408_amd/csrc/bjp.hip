@@ -297,23 +297,30 @@ void launch_small_t(int G, int res, const SmallArgs &a, size_t lds, hipStream_t 
     }
 }
 
-// What of the inverse packets and the CSR the one-workgroup solver keeps in
-// LDS beside its two vectors: the packets if they fit, then the CSR if it
-// fits too.
-int small_residency(const SmallArgs &a, bool has_m) {
-    const size_t vec = 2 * sizeof(double) * (size_t)a.n;
+// What of the inverse packets and the CSR a one-workgroup kernel keeps in
+// LDS beside its own `base` bytes: the packets if they fit, then the CSR if
+// it fits too.
+int small_residency(size_t base, int nnz, int tiles_bytes, bool has_m) {
     int res = 0;
-    if (has_m && vec + small_stage_bytes(kResTiles, a.nnz, a.tiles_bytes) <= kSmallLdsBytes) res |= kResTiles;
-    if (vec + small_stage_bytes(res | kResCsr, a.nnz, a.tiles_bytes) <= kSmallLdsBytes) res |= kResCsr;
+    if (has_m && base + small_stage_bytes(kResTiles, nnz, tiles_bytes) <= kSmallLdsBytes) res |= kResTiles;
+    if (base + small_stage_bytes(res | kResCsr, nnz, tiles_bytes) <= kSmallLdsBytes) res |= kResCsr;
     return res;
 }
 
+// bytes of the inverse packets (0 without a preconditioner)
+int precond_tiles_bytes(const bjp_precond_t *M) {
+    return M ? (int)((size_t)M->num_packets * packet_elems(M->group) *
+                     (M->precision == BJP_FP32_STORE ? sizeof(float) : sizeof(double)))
+             : 0;
+}
+
+// The one-workgroup solver keeps two n-vectors in LDS, then what of the
+// inverse packets and the CSR fits.
 void launch_small(const bjp_precond_t *M, SmallArgs a, hipStream_t s) {
-    a.tiles_bytes = M ? (int)((size_t)M->num_packets * packet_elems(M->group) *
-                              (M->precision == BJP_FP32_STORE ? sizeof(float) : sizeof(double)))
-                      : 0;
-    const int res = small_residency(a, M != nullptr);
-    const size_t lds = 2 * sizeof(double) * (size_t)a.n + small_stage_bytes(res, a.nnz, a.tiles_bytes);
+    a.tiles_bytes = precond_tiles_bytes(M);
+    const size_t base = 2 * sizeof(double) * (size_t)a.n;
+    const int res = small_residency(base, a.nnz, a.tiles_bytes, M != nullptr);
+    const size_t lds = base + small_stage_bytes(res, a.nnz, a.tiles_bytes);
     if (!M) {
         if (res & kResCsr) launch_one_workgroup(k_pcg_small<1, double, false, kResCsr>, lds, s, a);
         else launch_one_workgroup(k_pcg_small<1, double, false, 0>, lds, s, a);
@@ -326,24 +333,44 @@ void launch_small(const bjp_precond_t *M, SmallArgs a, hipStream_t s) {
 
 // The one-workgroup Lanczos keeps two n-vectors and the step's Gram
 // coefficients in LDS.
-template <typename TS>
-void launch_lanczos_small_t(int G, const LanczosSmallArgs &a, size_t lds, hipStream_t s) {
+template <typename TS, int RES>
+void launch_lanczos_small_g(int G, const LanczosSmallArgs &a, size_t lds, hipStream_t s) {
     switch (G) {
-        case 1: hipLaunchKernelGGL((k_lanczos_small<1, TS, true>), dim3(1), dim3(kSmallWG), lds, s, a); break;
-        case 2: hipLaunchKernelGGL((k_lanczos_small<2, TS, true>), dim3(1), dim3(kSmallWG), lds, s, a); break;
-        case 4: hipLaunchKernelGGL((k_lanczos_small<4, TS, true>), dim3(1), dim3(kSmallWG), lds, s, a); break;
-        case 8: hipLaunchKernelGGL((k_lanczos_small<8, TS, true>), dim3(1), dim3(kSmallWG), lds, s, a); break;
-        case 16: hipLaunchKernelGGL((k_lanczos_small<16, TS, true>), dim3(1), dim3(kSmallWG), lds, s, a); break;
-        case 32: hipLaunchKernelGGL((k_lanczos_small<32, TS, true>), dim3(1), dim3(kSmallWG), lds, s, a); break;
-        default: hipLaunchKernelGGL((k_lanczos_small<64, TS, true>), dim3(1), dim3(kSmallWG), lds, s, a); break;
+        case 1: launch_one_workgroup(k_lanczos_small<1, TS, true, RES>, lds, s, a); break;
+        case 2: launch_one_workgroup(k_lanczos_small<2, TS, true, RES>, lds, s, a); break;
+        case 4: launch_one_workgroup(k_lanczos_small<4, TS, true, RES>, lds, s, a); break;
+        case 8: launch_one_workgroup(k_lanczos_small<8, TS, true, RES>, lds, s, a); break;
+        case 16: launch_one_workgroup(k_lanczos_small<16, TS, true, RES>, lds, s, a); break;
+        case 32: launch_one_workgroup(k_lanczos_small<32, TS, true, RES>, lds, s, a); break;
+        default: launch_one_workgroup(k_lanczos_small<64, TS, true, RES>, lds, s, a); break;
     }
 }
 
-void launch_lanczos_small(const bjp_precond_t *M, const LanczosSmallArgs &a, hipStream_t s) {
-    const size_t lds = sizeof(double) * (2 * (size_t)a.n + (size_t)a.steps + 1);
-    if (!M) hipLaunchKernelGGL((k_lanczos_small<1, double, false>), dim3(1), dim3(kSmallWG), lds, s, a);
-    else if (M->precision == BJP_FP32_STORE) launch_lanczos_small_t<float>(M->group, a, lds, s);
-    else launch_lanczos_small_t<double>(M->group, a, lds, s);
+template <typename TS>
+void launch_lanczos_small_t(int G, int res, const LanczosSmallArgs &a, size_t lds, hipStream_t s) {
+    switch (res) {
+        case 0: launch_lanczos_small_g<TS, 0>(G, a, lds, s); break;
+        case kResTiles: launch_lanczos_small_g<TS, kResTiles>(G, a, lds, s); break;
+        case kResCsr: launch_lanczos_small_g<TS, kResCsr>(G, a, lds, s); break;
+        default: launch_lanczos_small_g<TS, kResTiles | kResCsr>(G, a, lds, s); break;
+    }
+}
+
+// The one-workgroup estimate keeps two n-vectors and the coefficients in
+// LDS, then what of the inverse packets and the CSR fits (small_residency).
+void launch_lanczos_small(const bjp_precond_t *M, LanczosSmallArgs a, hipStream_t s) {
+    a.tiles_bytes = precond_tiles_bytes(M);
+    const size_t base = sizeof(double) * (2 * (size_t)a.n + lanczos_coef_slots(a.steps));
+    const int res = small_residency(base, a.nnz, a.tiles_bytes, M != nullptr);
+    const size_t lds = base + small_stage_bytes(res, a.nnz, a.tiles_bytes);
+    if (!M) {
+        if (res & kResCsr) launch_one_workgroup(k_lanczos_small<1, double, false, kResCsr>, lds, s, a);
+        else launch_one_workgroup(k_lanczos_small<1, double, false, 0>, lds, s, a);
+    } else if (M->precision == BJP_FP32_STORE) {
+        launch_lanczos_small_t<float>(M->group, res, a, lds, s);
+    } else {
+        launch_lanczos_small_t<double>(M->group, res, a, lds, s);
+    }
 }
 
 // gs = lanes per row of the lane-group schedule; 0 = row-block streaming with
@@ -1314,6 +1341,7 @@ int bjp_kappa_estimate(const bjp_csr_t *A, const bjp_precond_t *M, const double 
     if (n <= kSmallMaxRows && (long long)A->nnz <= (long long)kSmallMaxMeanRow * n && steps <= kSmallMaxSteps) {
         LanczosSmallArgs la{};
         la.n = n;
+        la.nnz = (int)A->nnz;
         la.rp = A->row_ptr;
         la.ci = A->col_idx;
         la.val = A->val;

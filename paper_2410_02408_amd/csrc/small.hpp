@@ -55,8 +55,10 @@ struct SmallArgs {
 };
 
 // Totals of NQ per-thread values over the workgroup, in a fixed order; every
-// thread receives them.  Ends with a barrier, so `red` can be reused and every
-// store made before the call is visible to the whole workgroup after it.
+// thread receives them.  One barrier: every store made before the call is
+// visible to the whole workgroup after it.  `red` is read after that barrier,
+// so it must not be written again before every thread has passed another
+// barrier (callers alternate two buffers, or put a barrier between).
 template <int NQ, int WAVES = kSmallWaves>
 __device__ __forceinline__ void small_sum(double (&v)[NQ], double (*red)[WAVES]) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -72,7 +74,6 @@ __device__ __forceinline__ void small_sum(double (&v)[NQ], double (*red)[WAVES])
         for (int w = 0; w < WAVES; ++w) t += red[q][w];
         v[q] = t;
     }
-    __syncthreads();
 }
 
 // This thread's rows: row(u) = threadIdx.x + u * kSmallWG, u < kSmallR.
@@ -115,17 +116,51 @@ __device__ __forceinline__ void small_apply(int n, int nblocks, int num_packets,
     }
 }
 
+// z = M^-1 r for this thread's rows, in registers, when the blocks are
+// uniform of G rows (G = the group width): packet pk then holds rows 64 pk ..
+// 64 pk + 63, lane l row 64 pk + l, so wave w's packets w, w + kSmallWaves,
+// ... hold exactly the rows of its threads (row(k) = tid + k kSmallWG), and
+// no value crosses a thread.  The same operations in the same order as
+// small_apply, so the same results.
+template <int G, typename TS>
+__device__ __forceinline__ void small_apply_regs(int n, int num_packets, const void *tiles_,
+                                                 const double (&r)[kSmallR], double (&z)[kSmallR], double &rz,
+                                                 double &rr) {
+    constexpr int P = 64 / G, E = packet_elems(G);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane / G, i = lane % G;
+    const TS *tiles = static_cast<const TS *>(tiles_);
+#pragma unroll
+    for (int k = 0; k < kSmallR; ++k) {
+        const int pk = wave + k * kSmallWaves;   // the same for the whole wave
+        z[k] = 0.0;
+        if (pk < num_packets) {
+            const int s = (pk * P + g) * G;
+            const int nn = max(0, min(G, n - s));
+            const bool act = i < nn;
+            TS dv[G / 2 + 1];
+            packet_load<G, TS>(tiles + (size_t)pk * E, lane, g, i, dv);
+            const TS zv = packet_product<G, TS>(dv, g, i, nn, (TS)(act ? r[k] : 0.0));
+            if (act) {
+                z[k] = (double)zv;
+                rz += r[k] * z[k];
+                rr += r[k] * r[k];
+            }
+        }
+    }
+}
+
 // The vectors live in LDS and registers: u (the vector the products gather:
-// p, or x for a residual) and w (r before an application, z after it), n
-// doubles each; every thread keeps x, r and p of its own rows in registers
-// (q = A p of its rows goes to w, which is free until the next application)
-// and the extents of its rows' CSR entries.
-// Copies what RES names to LDS after the two vectors; the pointers then
-// refer to the copies.  Ends with a barrier.
+// p, or x for a residual) and w (r staged for an application whose blocks
+// cross threads, z after it), n doubles each; every thread keeps x, r, p, z
+// and q = A p of its own rows in registers and the extents of its rows' CSR
+// entries.
+// Copies what RES names to LDS at `rest` (16-byte aligned, after the
+// kernel's vectors); the pointers then refer to the copies.  Ends with a
+// barrier.
 template <int RES>
-__device__ __forceinline__ void small_stage(double *lds, int n, int nnz, int tiles_bytes, const void *&tiles,
+__device__ __forceinline__ void small_stage(char *rest, int nnz, int tiles_bytes, const void *&tiles,
                                             const double *&val, const int32_t *&ci) {
-    char *rest = reinterpret_cast<char *>(lds + 2 * (size_t)n);
     if constexpr ((RES & kResTiles) != 0) {
         const uint4 *src = static_cast<const uint4 *>(tiles);
         uint4 *dst = reinterpret_cast<uint4 *>(rest);
@@ -155,20 +190,28 @@ template <int G, typename TS, bool HAS_M, int RES>
 __global__ __launch_bounds__(kSmallWG) void k_pcg_small(SmallArgs a) {
     extern __shared__ double lds[];
     double *u = lds, *w = lds + a.n;
-    __shared__ double red[2][kSmallWaves];
+    __shared__ double red[2][2][kSmallWaves];   // two buffers, used in turn
     const int tid = threadIdx.x, n = a.n;
+    int rb = 0;
+    auto sum = [&](auto &v) {
+        small_sum(v, red[rb]);
+        rb ^= 1;
+    };
+    // uniform blocks as wide as the group: the application stays in registers
+    // (groups of up to 16 lanes; wider packets leave too few registers)
+    const bool aligned = HAS_M && G <= 16 && a.uniform_nb == G;
     const void *tiles = a.tiles;
     const double *val = a.val;
     const int32_t *ci = a.ci;
-    small_stage<RES>(lds, n, a.nnz, a.tiles_bytes, tiles, val, ci);
+    small_stage<RES>(reinterpret_cast<char *>(lds + 2 * (size_t)n), a.nnz, a.tiles_bytes, tiles, val, ci);
     int kb[kSmallR], ke[kSmallR];
-    double x[kSmallR], r[kSmallR], p[kSmallR];
+    double x[kSmallR], r[kSmallR], p[kSmallR], z[kSmallR];
 #pragma unroll
     for (int k = 0; k < kSmallR; ++k) {
         const int i = tid + k * kSmallWG;
         kb[k] = i < n ? a.rp[i] : 0;
         ke[k] = i < n ? a.rp[i + 1] : 0;
-        x[k] = r[k] = p[k] = 0.0;
+        x[k] = r[k] = p[k] = z[k] = 0.0;
     }
     // (A u) of this thread's row k, entries in storage order
     auto row = [&](int k) {
@@ -211,29 +254,42 @@ __global__ __launch_bounds__(kSmallWG) void k_pcg_small(SmallArgs a) {
                 v[1] += r[k] * r[k];
             }
         }
-        small_sum<2>(v, red);
+        sum(v);
         finish_decide<FIN_RESID_START>(f, &L, nullptr, v);
     }
-    // w = r, z = M^-1 r in w; this thread's share of r^T z (and r^T r)
+    // z = M^-1 r (in registers, or in w until fetch_z after the next
+    // barrier); this thread's share of r^T z (and r^T r)
     auto precondition = [&](double &rz, double &rr) {
         if constexpr (HAS_M) {
+            if (aligned) {
+                if constexpr (G <= 16) small_apply_regs<G, TS>(n, a.num_packets, tiles, r, z, rz, rr);
+            } else {
 #pragma unroll
-            for (int k = 0; k < kSmallR; ++k) {
-                const int i = tid + k * kSmallWG;
-                if (i < n) w[i] = r[k];
+                for (int k = 0; k < kSmallR; ++k) {
+                    const int i = tid + k * kSmallWG;
+                    if (i < n) w[i] = r[k];
+                }
+                __syncthreads();   // r complete before the packets read it
+                small_apply<G, TS>(a.n, a.nblocks, a.num_packets, a.uniform_nb, a.off, tiles, w, rz, rr);
             }
-            __syncthreads();   // r complete before the packets read it
-            small_apply<G, TS>(a.n, a.nblocks, a.num_packets, a.uniform_nb, a.off, tiles, w, rz, rr);
         } else {
 #pragma unroll
             for (int k = 0; k < kSmallR; ++k) {
                 const int i = tid + k * kSmallWG;
-                if (i < n) {
-                    w[i] = r[k];
-                    rz += r[k] * r[k];
-                }
+                z[k] = r[k];
+                if (i < n) rz += r[k] * r[k];
             }
             rr = rz;
+        }
+    };
+    // z of this thread's rows from w (written by other lanes: after a barrier)
+    auto fetch_z = [&]() {
+        if (HAS_M && !aligned) {
+#pragma unroll
+            for (int k = 0; k < kSmallR; ++k) {
+                const int i = tid + k * kSmallWG;
+                z[k] = i < n ? w[i] : 0.0;
+            }
         }
     };
     int repl = 0;
@@ -243,14 +299,15 @@ __global__ __launch_bounds__(kSmallWG) void k_pcg_small(SmallArgs a) {
             double v[1] = {0.0};
             double rr = 0.0;
             precondition(v[0], rr);
-            small_sum<1>(v, red);
+            sum(v);
             finish_decide<FIN_PCG_START>(f, &L, nullptr, v);
             if (!L.done) {
+                fetch_z();
 #pragma unroll
                 for (int k = 0; k < kSmallR; ++k) {
                     const int i = tid + k * kSmallWG;
                     if (i < n) {
-                        p[k] = w[i];
+                        p[k] = z[k];
                         u[i] = p[k];
                     }
                 }
@@ -258,18 +315,19 @@ __global__ __launch_bounds__(kSmallWG) void k_pcg_small(SmallArgs a) {
         }
         while (!L.done) {
             __syncthreads();   // p complete in u before it is gathered
-            // q = A p, parked in w (free until the next application) by its owner
+            // q = A p
             double sg[1] = {0.0};
+            double q[kSmallR];
 #pragma unroll
             for (int k = 0; k < kSmallR; ++k) {
                 const int i = tid + k * kSmallWG;
+                q[k] = 0.0;
                 if (i < n) {
-                    const double qi = row(k);
-                    w[i] = qi;
-                    sg[0] += p[k] * qi;
+                    q[k] = row(k);
+                    sg[0] += p[k] * q[k];
                 }
             }
-            small_sum<1>(sg, red);
+            sum(sg);
             finish_decide<FIN_SIGMA>(f, &L, nullptr, sg);
             if (L.done) break;
             const double alpha = L.alpha;
@@ -278,26 +336,27 @@ __global__ __launch_bounds__(kSmallWG) void k_pcg_small(SmallArgs a) {
                 const int i = tid + k * kSmallWG;
                 if (i < n) {
                     x[k] = __builtin_fma(alpha, p[k], x[k]);
-                    r[k] = __builtin_fma(-alpha, w[i], r[k]);
+                    r[k] = __builtin_fma(-alpha, q[k], r[k]);
                 }
             }
             double t[2] = {0.0, 0.0};
             precondition(t[0], t[1]);
             if constexpr (HAS_M) {
-                small_sum<2>(t, red);
+                sum(t);
                 finish_decide<FIN_PCG_UPDATE>(f, &L, nullptr, t);
             } else {
                 double t1[1] = {t[0]};
-                small_sum<1>(t1, red);
+                sum(t1);
                 finish_decide<FIN_PCG_UPDATE_I>(f, &L, nullptr, t1);
             }
             if (!L.done) {
+                fetch_z();
                 const double beta = L.beta;
 #pragma unroll
                 for (int k = 0; k < kSmallR; ++k) {
                     const int i = tid + k * kSmallWG;
                     if (i < n) {
-                        p[k] = __builtin_fma(beta, p[k], w[i]);
+                        p[k] = __builtin_fma(beta, p[k], z[k]);
                         u[i] = p[k];
                     }
                 }
@@ -329,7 +388,7 @@ __global__ __launch_bounds__(kSmallWG) void k_pcg_small(SmallArgs a) {
                     v[1] += r[k] * r[k];
                 }
             }
-            small_sum<2>(v, red);
+            sum(v);
             finish_decide<FIN_RESID_TRUE>(f, &L, nullptr, v);
         }
         if (L.status != BJP_OK || L.relres_true <= L.tol) break;
@@ -377,6 +436,9 @@ __global__ __launch_bounds__(kSmallWG) void k_pcg_small(SmallArgs a) {
 constexpr int kLzUnroll = 8;                  // basis vectors per round of the update loop
 constexpr int kLzDotLoads = 32;               // basis loads in flight per lane in the dot loop
 constexpr int kSmallMaxSteps = 2048;          // the coefficients live in LDS
+// LDS doubles for the coefficients (steps + 1, even, so what follows is
+// 16-byte aligned)
+__host__ __device__ constexpr int lanczos_coef_slots(int steps) { return (steps + 2) & ~1; }
 
 // Wave totals of UN per-lane values at once (UN a power of two, at most 64).
 // In each of the first log2(UN) butterfly stages a lane keeps half of its
@@ -407,7 +469,8 @@ __device__ __forceinline__ double wave_sums_transposed(double (&s)[UN]) {
 }
 
 struct LanczosSmallArgs {
-    int n;
+    int n, nnz;
+    int tiles_bytes;     // bytes of the inverse packets (copied to LDS with kResTiles)
     const int32_t *rp, *ci;
     const double *val;
     int nblocks, num_packets, uniform_nb;
@@ -421,7 +484,7 @@ struct LanczosSmallArgs {
     LanczosState *ls;    // the final state (read by k_tridiag and the host)
 };
 
-template <int G, typename TS, bool HAS_M>
+template <int G, typename TS, bool HAS_M, int RES>
 __global__ __launch_bounds__(kSmallWG) void k_lanczos_small(LanczosSmallArgs a) {
     constexpr int WG = kSmallWG, W = kSmallWaves, R = kSmallR;
     extern __shared__ double lds[];
@@ -429,6 +492,11 @@ __global__ __launch_bounds__(kSmallWG) void k_lanczos_small(LanczosSmallArgs a) 
     double *vg = lds, *w = lds + n, *cf = lds + 2 * n;   // gathered vector / staged r~, z~, coefficients
     __shared__ double sred[1][W];
     __shared__ LanczosState S;
+    const void *tiles = a.tiles;
+    const double *val = a.val;
+    const int32_t *ci = a.ci;
+    small_stage<RES>(reinterpret_cast<char *>(cf + lanczos_coef_slots(a.steps)), a.nnz, a.tiles_bytes, tiles, val,
+                     ci);
     int kb[R], ke[R];
     double r[R], z[R], uj[R], up[R];
 #pragma unroll
@@ -536,7 +604,7 @@ __global__ __launch_bounds__(kSmallWG) void k_lanczos_small(LanczosSmallArgs a) 
             }
             __syncthreads();
             double rr = 0.0;
-            small_apply<G, TS>(a.n, a.nblocks, a.num_packets, a.uniform_nb, a.off, a.tiles, w, rz, rr);
+            small_apply<G, TS>(a.n, a.nblocks, a.num_packets, a.uniform_nb, a.off, tiles, w, rz, rr);
             __syncthreads();
 #pragma unroll
             for (int k = 0; k < R; ++k) {
@@ -587,7 +655,7 @@ __global__ __launch_bounds__(kSmallWG) void k_lanczos_small(LanczosSmallArgs a) 
             for (int k = 0; k < R; ++k) {
                 if (tid + k * WG < n) {
                     double acc = 0.0;
-                    for (int e = kb[k]; e < ke[k]; ++e) acc += a.val[e] * vg[a.ci[e]];
+                    for (int e = kb[k]; e < ke[k]; ++e) acc += val[e] * vg[ci[e]];
                     r[k] = acc;   // w, turned into r~ below
                     v[0] += vg[tid + k * WG] * acc;
                 }

@@ -656,6 +656,30 @@ def test_one_workgroup_solver_matches_oracle(gpu, orc, name, make, nb, kind):
     assert abs(true - info.rel_res_true) <= 1e-13
 
 
+@pytest.mark.parametrize("nb", [1, 4, 16])
+def test_one_workgroup_register_application(gpu, nb):
+    """Uniform blocks as wide as their lane group are applied in registers by
+    the one-workgroup solver; the same blocks given as explicit offsets go
+    through LDS.  Both are the same operations in the same order: equal
+    iteration counts, residual histories and solutions, bit for bit (900 rows:
+    a ragged last block)."""
+    A = w.poisson2d(30)
+    b = w.rhs(A.n, 91)
+    Ad = dev(A)
+    off = list(range(0, A.n, nb)) + [A.n]
+    Mu = gpu.precondition(Ad, block_size=nb)
+    Me = gpu.precondition(Ad, offsets=off)
+    hu = torch.full((A.n + 1,), float("nan"), dtype=torch.float64, device=DEV)
+    he = hu.clone()
+    xu, iu = gpu.pcg_solve(Ad, Mu, b, history=hu)
+    xe, ie = gpu.pcg_solve(Ad, Me, b, history=he)
+    assert iu.status == ie.status == "OK" and iu.polls == ie.polls == 1
+    assert iu.iterations == ie.iterations
+    k = iu.iterations + 1
+    assert torch.equal(hu[:k], he[:k])
+    assert torch.equal(xu, xe)
+
+
 def test_one_workgroup_limit(gpu):
     """2049 rows take the multi-launch solver (several polls at a cadence of
     one iteration), 2048 the one-workgroup solver."""
