@@ -40,6 +40,8 @@ def parse():
                     help="iterations of the single-threaded oracle sample")
     ap.add_argument("--cpu-single-full", action="store_true",
                     help="time the single-threaded oracle over the full solve too")
+    ap.add_argument("--cpu-min-s", type=float, default=5.0,
+                    help="repeat each oracle sample until it lasts this long (small systems)")
     ap.add_argument("--oracle-check", action="store_true",
                     help="solve with the (sequential) oracle and report the GPU's error against it")
     ap.add_argument("--no-oracle", action="store_true",
@@ -589,33 +591,45 @@ def cpu_baseline(W, args) -> dict:
     """The oracle on this host's cores, on the same system: the OpenMP timing
     build over the full solve to tol on all available threads (the value),
     and the sequential build over a bounded sample of iterations (or the full
-    solve with --cpu-single-full).  Setup is timed separately."""
+    solve with --cpu-single-full), each repeated until it lasts --cpu-min-s.
+    Setup is timed separately."""
     import oracle
+
+    def repeated(solve):
+        # the same solve again until the sample lasts --cpu-min-s (small
+        # systems), unless one more would take it past 1.5 times that
+        reps, t0 = 0, time.time()
+        while True:
+            r = solve()
+            reps += 1
+            dt = time.time() - t0
+            if dt >= args.cpu_min_s or dt * (reps + 1) / reps > 1.5 * args.cpu_min_s:
+                return r, reps, dt
+
+    def times(reps):
+        return "" if reps == 1 else f", {reps} times"
 
     host = host_cpu()
     with oracle.timing_threads(0) as threads:
         t = time.time()
         Mo = oracle.Precond.uniform(W.A, W.block_size)
         setup_s = time.time() - t
-        t = time.time()
-        r = oracle.pcg(W.A, W.b, Mo, tol=W.tol)
-        dt = time.time() - t
+        r, reps, dt = repeated(lambda: oracle.pcg(W.A, W.b, Mo, tol=W.tol))
     del Mo
     Mo = oracle.Precond.uniform(W.A, W.block_size)
     single_iters = None if args.cpu_single_full else args.cpu_iters
-    t = time.time()
-    r1 = oracle.pcg(W.A, W.b, Mo, tol=W.tol, max_iter=single_iters,
-                    max_replacements=3 if single_iters is None else 0)
-    dt1 = time.time() - t
-    what1 = "the full solve" if single_iters is None else f"{r1.iterations} iterations"
+    r1, reps1, dt1 = repeated(lambda: oracle.pcg(W.A, W.b, Mo, tol=W.tol, max_iter=single_iters,
+                                                 max_replacements=3 if single_iters is None else 0))
+    what1 = "the full solve" if single_iters is None or r1.iterations < single_iters else f"{r1.iterations} iterations"
     return {
-        "value": round(r.iterations / dt, 3), "unit": "PCG iterations/s", "cores": threads, "kind": "oracle",
+        "value": round(reps * r.iterations / dt, 3), "unit": "PCG iterations/s", "cores": threads, "kind": "oracle",
         "sample": (f"full solve of the same {args.workload} system to {W.tol:g} ({r.iterations} iterations, "
-                   f"{r.status}, {dt:.1f} s) by the oracle's OpenMP timing build on {threads} threads; "
-                   f"its block setup took {setup_s:.1f} s, not included"),
+                   f"{r.status}{times(reps)}, {dt:.1f} s) by the oracle's OpenMP timing build on {threads} "
+                   f"threads; its block setup took {setup_s:.1f} s, not included"),
         "host": host,
-        "single_thread": {"value": round(r1.iterations / dt1, 3), "cores": 1,
-                          "sample": f"{what1} of the same system by the sequential oracle ({dt1:.1f} s)"},
+        "single_thread": {"value": round(reps1 * r1.iterations / dt1, 3), "cores": 1,
+                          "sample": (f"{what1} of the same system by the sequential oracle"
+                                     f"{times(reps1)} ({dt1:.1f} s)")},
     }
 
 
