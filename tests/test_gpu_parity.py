@@ -250,6 +250,27 @@ def test_pcg_single_block_one_iteration(gpu, lanes):
 
 
 @BOTH_SOLVERS
+@pytest.mark.parametrize("n,nb", [(20, 64), (5, 64), (33, 40)])
+def test_block_wider_than_system(gpu, lanes, n, nb):
+    """A requested block size above n gives one block spanning A (the group
+    sized for n, e.g. 32 lanes for 20 rows): M^-1 = A^-1, so the application
+    solves with A, PCG converges in one iteration and kappa(M^-1 A) = 1."""
+    A = w.laplacian1d(n)
+    Ad = dev(A)
+    M = gpu.precondition(Ad, block_size=nb)
+    assert M.offsets().tolist() == [0, n]
+    dense = A.to_dense()
+    r = w.rhs(n, 93)
+    z = gpu.apply(M, torch.as_tensor(r, device=DEV))
+    np.testing.assert_allclose(z.cpu().numpy(), np.linalg.solve(dense, r), rtol=1e-11, atol=1e-12)
+    x, info = gpu.pcg_solve(Ad, M, r, spmv_lanes=lanes)
+    assert info.status == "OK" and info.iterations == 1
+    np.testing.assert_allclose(x.cpu().numpy(), np.linalg.solve(dense, r), rtol=1e-11, atol=1e-12)
+    k = gpu.kappa_estimate(Ad, r, 10, M)
+    assert k.status == "OK" and k.steps == 1 and abs(k.kappa - 1) < 1e-12
+
+
+@BOTH_SOLVERS
 def test_pcg_deterministic(gpu, lanes):
     W = w.workload("diffusion3d_12")
     A = dev(W.A)
