@@ -1447,7 +1447,11 @@ int bjp_kappa_estimate(const bjp_csr_t *A, const bjp_precond_t *M, const double 
             }
         }
     }
-    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(64), 0, stream, ls, al, be);
+    {
+        const int lds_steps = steps <= kTriLdsSteps ? steps : 0;
+        hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(64 * kTriWaves), sizeof(double) * 2 * (size_t)lds_steps, stream,
+                           ls, al, be, lds_steps);
+    }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(&h, ls, sizeof(h), hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));

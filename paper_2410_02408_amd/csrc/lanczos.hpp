@@ -169,16 +169,15 @@ __global__ __launch_bounds__(kWG) void k_gram_reduce(LanczosState *ls, const dou
 
 // Number of eigenvalues of T = tridiag(beta; alpha; beta) below x: negative
 // pivots of the LDL^T factorisation of T - x I (pivots below pivmin in size
-// are pushed to -pivmin).
-__device__ int sturm_count(const double *al, const double *be, int s, double x, double pivmin) {
-    int cnt = 0;
+// are pushed to -pivmin).  b2[i] = beta_i^2.
+__device__ __forceinline__ int sturm_count(const double *al, const double *b2, int s, double x, double pivmin) {
     double d = al[0] - x;
     if (fabs(d) < pivmin) d = -pivmin;
-    if (d < 0.0) ++cnt;
+    int cnt = d < 0.0 ? 1 : 0;
     for (int i = 1; i < s; ++i) {
-        d = al[i] - x - be[i - 1] * be[i - 1] / d;
+        d = al[i] - x - b2[i - 1] / d;
         if (fabs(d) < pivmin) d = -pivmin;
-        if (d < 0.0) ++cnt;
+        cnt += d < 0.0 ? 1 : 0;
     }
     return cnt;
 }
@@ -195,22 +194,48 @@ __device__ double wave_max(double v) {
 }
 
 // Extreme eigenvalues of the s x s Lanczos tridiagonal by Sturm-count
-// multisection: each round the 64 lanes probe 64 interior points of the
-// current bracket, which shrinks it 65-fold.  One wave.
-__global__ __launch_bounds__(64) void k_tridiag(LanczosState *ls, const double *al, const double *be) {
+// multisection.  Waves 0-3 bracket the smallest eigenvalue, waves 4-7 the
+// largest, at the same time.  Each round the 256 lanes of a group probe 256
+// interior points of its bracket (one each: a probe's recurrence is a chain
+// of divisions, so more probes per lane would only queue behind it), which
+// shrinks the bracket 257-fold; the waves of a group exchange their first
+// hits through LDS.  Every wave takes every round's barrier, a converged
+// group included, until both groups have converged.  alpha and beta^2 are
+// staged in LDS when the launch gives room (lds_steps >= s, 16 bytes a step).
+constexpr int kTriWaves = 8;
+constexpr int kTriLdsSteps = 4096;   // the launch stages up to this many steps (64 KB)
+
+__global__ __launch_bounds__(64 * kTriWaves) void k_tridiag(LanczosState *ls, const double *al_g, const double *be_g,
+                                                            int lds_steps) {
+    constexpr int GW = kTriWaves / 2;   // waves per group
+    constexpr int NP = 64 * GW;         // probes per group and round
+    extern __shared__ double tl[];      // alpha [lds_steps], then beta^2 [lds_steps]
+    __shared__ int firsts[2][2][GW];    // [round parity][group][wave]: first hit, NP none, -1 converged
+    __shared__ double res[2];
     const int s = ls->steps_done;
     if (ls->status != BJP_OK || s <= 0) return;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int group = wave / GW, wig = wave % GW;
+    const bool staged = s <= lds_steps;
+    double *b2 = tl + lds_steps;
+    if (staged) {
+        for (int i = tid; i < s; i += 64 * kTriWaves) {
+            tl[i] = al_g[i];
+            if (i + 1 < s) b2[i] = be_g[i] * be_g[i];
+        }
+    }
+    __syncthreads();
+    // Gershgorin interval (every wave forms the same one, in the same order)
     double glo = INFINITY, ghi = -INFINITY, bmax = 1.0;
     for (int i = lane; i < s; i += 64) {
         double rad = 0.0;
-        if (i > 0) rad += fabs(be[i - 1]);
+        if (i > 0) rad += fabs(be_g[i - 1]);
         if (i + 1 < s) {
-            rad += fabs(be[i]);
-            bmax = fmax(bmax, be[i] * be[i]);
+            rad += fabs(be_g[i]);
+            bmax = fmax(bmax, be_g[i] * be_g[i]);
         }
-        glo = fmin(glo, al[i] - rad);
-        ghi = fmax(ghi, al[i] + rad);
+        glo = fmin(glo, al_g[i] - rad);
+        ghi = fmax(ghi, al_g[i] + rad);
     }
     glo = wave_min(glo);
     ghi = wave_max(ghi);
@@ -218,28 +243,49 @@ __global__ __launch_bounds__(64) void k_tridiag(LanczosState *ls, const double *
     const double eps = 2.220446049250313e-16;
     const double pivmin = 2.2250738585072014e-308 * bmax;
     const double widen = 4.0 * eps * (fabs(glo) + fabs(ghi) + (ghi - glo)) * s + 2.0 * pivmin;
-    glo -= widen;
-    ghi += widen;
-    double res[2];
-    for (int which = 0; which < 2; ++which) {
-        const int target = which == 0 ? 1 : s;
-        double lo = glo, hi = ghi;
-        for (int round = 0; round < 64; ++round) {
-            if (hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi)) || hi - lo <= pivmin) break;
-            const double h = (hi - lo) / 65.0;
-            const double xl = lo + h * (lane + 1);
-            const int cnt = sturm_count(al, be, s, xl, pivmin);
+    const int target = group == 0 ? 1 : s;
+    double lo = glo - widen, hi = ghi + widen;
+    for (int round = 0; round < 64; ++round) {
+        const int par = round & 1;
+        const bool conv = hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi)) || hi - lo <= pivmin;
+        const double h = (hi - lo) / (NP + 1.0);
+        if (!conv) {
+            const double x = lo + h * (wig * 64 + lane + 1);
+            int cnt;
+            if (staged) {
+                cnt = sturm_count(tl, b2, s, x, pivmin);
+            } else {
+                // beta^2 formed per step, the same product as the staged one
+                double d = al_g[0] - x;
+                if (fabs(d) < pivmin) d = -pivmin;
+                cnt = d < 0.0 ? 1 : 0;
+                for (int i = 1; i < s; ++i) {
+                    d = al_g[i] - x - (be_g[i - 1] * be_g[i - 1]) / d;
+                    if (fabs(d) < pivmin) d = -pivmin;
+                    cnt += d < 0.0 ? 1 : 0;
+                }
+            }
             const unsigned long long hit = __ballot(cnt >= target);
-            // first probe that has reached the target count
-            const int first = hit ? __ffsll((long long)hit) - 1 : 64;
+            if (lane == 0) firsts[par][group][wig] = hit ? wig * 64 + __ffsll((long long)hit) - 1 : NP;
+        } else if (lane == 0) {
+            firsts[par][group][wig] = -1;
+        }
+        __syncthreads();
+        if (firsts[par][0][0] < 0 && firsts[par][1][0] < 0) break;   // the same for every thread
+        if (!conv) {
+            // the first probe (in order) that reached the target count
+            int first = NP;
+#pragma unroll
+            for (int w = 0; w < GW; ++w) first = min(first, firsts[par][group][w]);
             const double nlo = first == 0 ? lo : lo + h * first;
-            const double nhi = first == 64 ? hi : lo + h * (first + 1);
+            const double nhi = first == NP ? hi : lo + h * (first + 1);
             lo = nlo;
             hi = nhi;
         }
-        res[which] = 0.5 * (lo + hi);
     }
-    if (lane == 0) {
+    if (wig == 0 && lane == 0) res[group] = 0.5 * (lo + hi);
+    __syncthreads();
+    if (tid == 0) {
         ls->theta_min = res[0];
         ls->theta_max = res[1];
         ls->kappa = res[1] / res[0];

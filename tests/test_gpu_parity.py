@@ -385,6 +385,29 @@ def test_kappa_many_steps_tiles(gpu, orc, n):
     assert abs(k.kappa - ko.kappa) <= 1e-6 * ko.kappa
 
 
+@pytest.mark.parametrize("n,steps", [(1000, 60), (1000, 5000), (3000, 60), (3000, 5000)],
+                         ids=["1000 rows, 60 steps (one workgroup)", "1000 rows, 5000 steps (multi-launch)",
+                              "3000 rows, 60 steps", "3000 rows, 5000 steps"])
+def test_kappa_tridiagonal_extremes(gpu, orc, n, steps):
+    """A diagonal matrix with ten evenly spaced eigenvalues 1..10 (each n/10
+    times): Lanczos breaks down after ten steps and its Ritz extremes are the
+    exact extremes, kappa = 10.  The multisection's results equal the extreme
+    eigenvalues of the returned tridiagonal (numpy), with the tridiagonal
+    staged in LDS (60 steps) and read from global memory (5000 steps, above
+    the staging limit)."""
+    vals = np.repeat(np.linspace(1.0, 10.0, 10), n // 10)
+    A = w.from_coo(n, np.arange(n), np.arange(n), vals)
+    b = w.rhs(n, 95)
+    k = gpu.kappa_estimate(dev(A), b, steps)
+    ko = orc.kappa(A, b, steps)
+    assert k.status == ko.status == "OK" and k.steps == ko.steps == 10
+    T = np.diag(k.alpha) + np.diag(k.beta, 1) + np.diag(k.beta, -1)
+    ev = np.linalg.eigvalsh(T)
+    assert abs(k.theta_min - ev[0]) <= 1e-13 * ev[-1] and abs(k.theta_max - ev[-1]) <= 1e-13 * ev[-1]
+    assert abs(k.kappa - 10.0) <= 1e-9 * 10.0
+    assert abs(k.kappa - ko.kappa) <= 1e-10 * ko.kappa
+
+
 KAPPA_SMALL = [("poisson2d_32 fp32-stored", lambda: (w.poisson2d(32), w.rhs(1024, 0)), 16, "fp32", 100),
                ("random_spd_777 explicit blocks", lambda: (w.random_spd(777, np.random.default_rng(81)),
                                                            w.rhs(777, 85)), 0, "explicit", 120),
