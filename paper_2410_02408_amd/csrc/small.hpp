@@ -7,11 +7,13 @@
 // scalar decisions (finish_decide) and stopping rule, true-residual check and
 // residual replacement as bjp_pcg_solve, with workgroup barriers between the
 // phases instead of kernel boundaries.  Thread t owns rows t, t + kSmallWG,
-// ...: it keeps their x, r, p in registers, forms their products row by
-// row (entries in storage order) gathering from the direction held in LDS;
+// ...: it keeps their x, r, p, z and q in registers, forms their products row
+// by row (entries in storage order) gathering from the direction held in LDS;
 // the block-inverse application runs packet by packet on the waves (wave w
-// takes packets w, w + kSmallWaves, ...) on r staged in LDS.  Every total is
-// a fixed-order workgroup reduction, so the solve is deterministic.  Only the
+// takes packets w, w + kSmallWaves, ...), in registers when the blocks are
+// uniform and as wide as their lane group (a packet's rows are then its
+// lanes' own rows), else on r staged in LDS.  Every total is a fixed-order
+// workgroup reduction, so the solve is deterministic.  Only the
 // matrix and the block inverses are read in an iteration, and one workgroup
 // streams them from L2 at only about 60 GB/s, so whatever of them fits in
 // LDS beside the vectors (the inverse packets first, then the CSR values and
@@ -429,9 +431,10 @@ __global__ __launch_bounds__(kSmallWG) void k_pcg_small(SmallArgs a) {
 //     either way, which bounds the estimate at 1024 rows and 100 steps,
 //     165 MB of basis reads, near 2.7 ms).
 // The vector the product gathers, r~ / z~ of the application and the
-// coefficients are staged in LDS, each thread's rows of r, z, u_j, u_{j-1}
-// in registers.  The scalar decisions are taken by thread 0 on a state in LDS
-// that every thread then reads.
+// coefficients are staged in LDS, and after them whatever of the inverse
+// packets and the CSR fits (as in the solver); each thread's rows of r, z,
+// u_j, u_{j-1} are in registers.  The scalar decisions are taken by thread 0
+// on a state in LDS that every thread then reads.
 // ---------------------------------------------------------------------------
 constexpr int kLzUnroll = 8;                  // basis vectors per round of the update loop
 constexpr int kLzDotLoads = 32;               // basis loads in flight per lane in the dot loop

@@ -488,26 +488,29 @@ def test_pcg_warm_start_matches_oracle(gpu, orc, lanes):
     assert np.linalg.norm(x.cpu().numpy() - ref.x) / np.linalg.norm(ref.x) <= 1e-10
 
 
-def test_pcg_streaming_long_and_empty_rows(gpu, orc):
-    """Row-block streaming with a row far longer than one LDS stage (a hub row
-    coupled to 3000 others) and rows with only a diagonal."""
-    n = 4000
+@pytest.mark.parametrize("n,hub_deg", [(4000, 3000), (2000, 1500)],
+                         ids=["4000 rows (multi-launch)", "2000 rows (one workgroup with the automatic schedule)"])
+def test_pcg_streaming_long_and_empty_rows(gpu, orc, n, hub_deg):
+    """A row far longer than one LDS stage of the row-block streaming (a hub
+    row coupled to most others) and rows with only a diagonal, under the
+    streaming schedule and the automatic one (at 2000 rows the one-workgroup
+    solver, whose thread takes the hub row alone)."""
     rng = np.random.default_rng(22)
     hub = 1234
-    others = np.setdiff1d(rng.choice(n, 3000, replace=False), [hub])
+    others = np.setdiff1d(rng.choice(n, hub_deg, replace=False), [hub])
     pi = np.concatenate([np.arange(n - 1), np.full(len(others), hub)])     # one entry per pair
     pj = np.concatenate([np.arange(1, n), others])
-    keep = (pi < 3900) & (pj < 3900)                                        # rows >= 3900: diagonal only
+    keep = (pi < n - 100) & (pj < n - 100)                                  # the last 100 rows: diagonal only
     pi, pj = pi[keep], pj[keep]
     pv = -rng.random(len(pi))
     rows, cols, vals = np.concatenate([pi, pj]), np.concatenate([pj, pi]), np.concatenate([pv, pv])
     diag = np.bincount(rows, weights=np.abs(vals), minlength=n) + 0.5
     A = w.from_coo(n, np.concatenate([rows, np.arange(n)]), np.concatenate([cols, np.arange(n)]),
                    np.concatenate([vals, diag]))
-    assert np.diff(A.row_ptr).max() > 2048 and A.nnz / n < 12
+    assert np.diff(A.row_ptr).max() > 1024 + 256 and A.nnz / n < 12
     b = w.rhs(n, 23)
     for lanes in (-1, 0):
-        _pcg_parity(gpu, orc, A, b, 16, case="hub_4000/16", spmv_lanes=lanes)
+        _pcg_parity(gpu, orc, A, b, 16, case=f"hub_{n}/16", spmv_lanes=lanes)
 
 
 def test_torch_sparse_csr_input(gpu):
