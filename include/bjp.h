@@ -194,6 +194,10 @@ int bjp_pcg_workspace(const bjp_csr_t *A, size_t *bytes /* host out */);
  * one and iteration continues (up to max_replacements times).
  *   b: device [n], x: device [n] (in: x0 when opts->x0_given; out: solution,
  *   or the last iterate on BJP_ENOCONV / BJP_EBREAKDOWN).  b = 0 gives x = 0.
+ * Systems of at most 2048 rows (at most 32 entries per row on average) with
+ * spmv_lanes = 0 and no timing are solved in a single workgroup, the whole
+ * solve in one launch (the same steps and decisions; info->polls = 1 and
+ * check_every is not used).
  * Synchronises `stream`; `info` (host) is always filled. */
 int bjp_pcg_solve(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, double *x,
                   const bjp_pcg_opts_t *opts, void *ws, size_t ws_bytes,
@@ -251,7 +255,9 @@ int bjp_kappa_workspace(const bjp_csr_t *A, int steps, size_t *bytes /* host out
  * Gram-Schmidt applied twice), then the extreme eigenvalues of the
  * tridiagonal by Sturm-count multisection.  A step whose new off-diagonal is
  * below 1e-12 of the largest coefficient ends the run early (success).
- * alpha/beta (device [steps], optional) receive the tridiagonal.
+ * alpha/beta (device [steps], optional) receive the tridiagonal.  Systems of
+ * at most 2048 rows (at most 32 entries per row on average) with steps <=
+ * 2048 run the estimate in a single workgroup (the same steps).
  * Synchronises `stream`; `info` (host) is always filled. */
 int bjp_kappa_estimate(const bjp_csr_t *A, const bjp_precond_t *M, const double *v0,
                        int steps, double *alpha, double *beta, void *ws, size_t ws_bytes,
