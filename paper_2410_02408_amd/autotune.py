@@ -16,8 +16,12 @@ and a schedule that wins on one class alone can lose inside the whole batch
 per-class assignment is then timed on the whole batch against every single
 batch-wide schedule and kept only if it is the fastest.  Choices are cached in
 a JSON file keyed by class (or batch shape), precision and the library's
-source digest, in $BJP_CACHE_DIR or ~/.cache/bjp.  (Waves per workgroup are
-not tuned: every kernel runs four.)
+source digest, in $BJP_CACHE_DIR or ~/.cache/bjp.  Waves per workgroup are
+not a separate dimension: every kernel runs four, and a tile of T rows on four
+waves gives each wave the rows that a tile of 2T rows would on eight, so the
+tile-row candidates already span what the wave count would change (the row
+loops and reductions the batch shares with the single-system kernels are
+written for four waves).
 """
 from __future__ import annotations
 
