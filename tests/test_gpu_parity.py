@@ -271,6 +271,31 @@ def test_block_wider_than_system(gpu, lanes, n, nb):
 
 
 @BOTH_SOLVERS
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_tiny_systems(gpu, orc, lanes, n):
+    """Systems of one to three rows (most lanes of the one-workgroup kernels
+    idle, a single packet): plain CG and block-Jacobi PCG against a dense
+    solve and the oracle's iteration counts, kappa against the eigenvalues."""
+    A = w.laplacian1d(n) if n > 1 else w.from_coo(1, [0], [0], [4.0])
+    Ad = dev(A)
+    dense = A.to_dense()
+    b = w.rhs(n, 97)
+    xs = np.linalg.solve(dense, b)
+    ev = np.linalg.eigvalsh(dense)
+    for nb in (0, 1, 2):
+        Md = gpu.precondition(Ad, block_size=nb) if nb else None
+        Mo = orc.Precond.uniform(A, nb) if nb else None
+        x, info = gpu.pcg_solve(Ad, Md, b, spmv_lanes=lanes)
+        ref = orc.pcg(A, b, Mo)
+        assert info.status == ref.status == "OK" and info.iterations == ref.iterations
+        np.testing.assert_allclose(x.cpu().numpy(), xs, rtol=1e-12, atol=1e-14)
+    k = gpu.kappa_estimate(Ad, b, 10)
+    ko = orc.kappa(A, b, 10)
+    assert k.status == ko.status == "OK" and k.steps == ko.steps <= n
+    assert abs(k.kappa - ev[-1] / ev[0]) <= 1e-12 * ev[-1] / ev[0]
+
+
+@BOTH_SOLVERS
 def test_pcg_deterministic(gpu, lanes):
     W = w.workload("diffusion3d_12")
     A = dev(W.A)
