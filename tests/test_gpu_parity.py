@@ -398,16 +398,18 @@ def test_kappa_single_block_and_breakdown(gpu):
     assert k.status == "EBREAKDOWN"
 
 
-@pytest.mark.parametrize("n", [400, 2100], ids=["one-workgroup", "multi-launch"])
-def test_kappa_many_steps_tiles(gpu, orc, n):
+@pytest.mark.parametrize("n,steps", [(400, 300), (2100, 320)], ids=["one-workgroup", "multi-launch"])
+def test_kappa_many_steps_tiles(gpu, orc, n, steps):
     """More than one group of Gram coefficients (j > 256): 400 rows take the
-    one-workgroup estimate, 2100 the multi-launch one."""
+    one-workgroup estimate, 2100 the multi-launch one; equal step counts,
+    kappa within 1e-6 and the tridiagonal within 1e-8 of the oracle's."""
     A = w.random_spd(n, np.random.default_rng(11), shift=0.3)
     Ad = dev(A)
-    k = gpu.kappa_estimate(Ad, w.rhs(n, 21), 300)
-    ko = orc.kappa(A, w.rhs(n, 21), 300)
-    assert k.steps == ko.steps
+    k = gpu.kappa_estimate(Ad, w.rhs(n, 21), steps)
+    ko = orc.kappa(A, w.rhs(n, 21), steps)
+    assert k.steps == ko.steps == steps
     assert abs(k.kappa - ko.kappa) <= 1e-6 * ko.kappa
+    np.testing.assert_allclose(k.alpha, ko.alpha, rtol=1e-8, atol=1e-12)
 
 
 @pytest.mark.parametrize("n,steps", [(1000, 60), (1000, 5000), (3000, 60), (3000, 5000)],
