@@ -14,10 +14,10 @@
 // uniform and as wide as their lane group (a packet's rows are then its
 // lanes' own rows), else on r staged in LDS.  Every total is a fixed-order
 // workgroup reduction, so the solve is deterministic.  Only the
-// matrix and the block inverses are read in an iteration, and one workgroup
-// streams them from L2 at only about 60 GB/s, so whatever of them fits in
-// LDS beside the vectors (the inverse packets first, then the CSR values and
-// columns; 160 KB per workgroup on gfx950) is copied there once per solve.
+// matrix and the block inverses are read in an iteration; whatever of them
+// fits in LDS beside the vectors (the inverse packets first, then the CSR
+// values and columns; 160 KB per workgroup on gfx950) is copied there once
+// per solve, which takes their L2 round trips off every iteration.
 #pragma once
 
 #include <type_traits>
@@ -426,10 +426,9 @@ __global__ __launch_bounds__(kSmallWG) void k_pcg_small(SmallArgs a) {
 //     per pass through LDS), so each coefficient takes one wave reduction
 //     and no exchange between waves;
 //   r~ -= sum_l c_l u_l: by rows, each thread its own, l in order, with the
-//     loads of kLzUnroll basis vectors in flight (deeper rounds measured no
-//     faster: one workgroup streams the basis from L2 at about 60 GB/s
-//     either way, which bounds the estimate at 1024 rows and 100 steps,
-//     165 MB of basis reads, near 2.7 ms).
+//     loads of kLzUnroll basis vectors in flight (deeper rounds, and rounds
+//     reading basis vectors cached in LDS instead of L2, measured no faster:
+//     a round is bound by its own instruction and reduction latency).
 // The vector the product gathers, r~ / z~ of the application and the
 // coefficients are staged in LDS, and after them whatever of the inverse
 // packets and the CSR fits (as in the solver); each thread's rows of r, z,
