@@ -47,6 +47,34 @@ __device__ __forceinline__ int tile_of(const TileSpan &ts) {
     return ts.begin + xcd_chunk(blockIdx.x, gridDim.x);
 }
 
+// The batch's block setup, one launch per lane-group width: workgroup q
+// takes packet q of the width's systems taken in order; items[] lists those
+// systems with the index of each one's first packet (ascending).
+struct SetupSys {
+    long long off_base;   // index of the system's first block offset
+    long long tile0;      // first scalar of the system's packets
+    int nblocks, block_base, first_packet, pad;
+};
+
+template <int G, typename TS>
+__global__ __launch_bounds__(64) void k_setup_batch(SetupArgs base, const SetupSys *items, int count) {
+    const int q = blockIdx.x;
+    int lo = 0, hi = count - 1;   // the last system whose first packet is <= q
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].first_packet <= q) lo = mid;
+        else hi = mid - 1;
+    }
+    SetupArgs a = base;
+    a.off = base.off + items[lo].off_base;
+    a.nblocks = items[lo].nblocks;
+    a.tiles = static_cast<TS *>(base.tiles) + items[lo].tile0;
+    a.block_base = items[lo].block_base;
+    const int pk = q - items[lo].first_packet;
+    if constexpr (G >= 8) setup_reg_packet<G, TS>(a, pk);
+    else setup_lds_packet<G, TS>(a, pk);
+}
+
 template <int GS, int MODE>
 __global__ __launch_bounds__(kWG) void k_spmv_tiles(SpmvArgs a, TileSpan ts) {
     const int t = tile_of(ts);

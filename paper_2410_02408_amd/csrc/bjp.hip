@@ -558,7 +558,21 @@ int make_batch_plan(const bjp_csr_t *A, const bjp_batch_t *B, BatchPlan &P) {
 size_t batch_precond_bytes(const BatchPlan &P, int precision) {
     const size_t elem = precision == BJP_FP32_STORE ? 4 : 8;
     return al256(sizeof(SysInfo) * P.sys.size()) + al256(sizeof(int32_t) * (P.sys.size() + 1)) +
-           al256(sizeof(int32_t) * P.off.size()) + al256(P.tile_scalars * elem) + al256(64);
+           al256(sizeof(int32_t) * P.off.size()) + al256(P.tile_scalars * elem) + al256(64) +
+           al256(sizeof(SetupSys) * P.sys.size());
+}
+
+template <typename TS>
+void launch_setup_batch(int G, int grid, const SetupArgs &a, const SetupSys *items, int count, hipStream_t s) {
+    switch (G) {
+        case 1: hipLaunchKernelGGL((k_setup_batch<1, TS>), dim3(grid), dim3(64), 0, s, a, items, count); break;
+        case 2: hipLaunchKernelGGL((k_setup_batch<2, TS>), dim3(grid), dim3(64), 0, s, a, items, count); break;
+        case 4: hipLaunchKernelGGL((k_setup_batch<4, TS>), dim3(grid), dim3(64), 0, s, a, items, count); break;
+        case 8: hipLaunchKernelGGL((k_setup_batch<8, TS>), dim3(grid), dim3(64), 0, s, a, items, count); break;
+        case 16: hipLaunchKernelGGL((k_setup_batch<16, TS>), dim3(grid), dim3(64), 0, s, a, items, count); break;
+        case 32: hipLaunchKernelGGL((k_setup_batch<32, TS>), dim3(grid), dim3(64), 0, s, a, items, count); break;
+        default: hipLaunchKernelGGL((k_setup_batch<64, TS>), dim3(grid), dim3(64), 0, s, a, items, count); break;
+    }
 }
 
 // Packets per apply tile of the batched solver (16 per wave: the two-stage
@@ -1504,6 +1518,7 @@ int bjp_batch_precondition(const bjp_csr_t *A, const bjp_batch_t *B, int precisi
     char *tiles = cv.base + cv.used;
     cv.used += al256(P.tile_scalars * elem);
     int32_t *flags = cv.take<int32_t>(16);
+    SetupSys *items = cv.take<SetupSys>(S);
     M_out->num_systems = S;
     M_out->precision = precision;
     M_out->systems = sys;
@@ -1516,12 +1531,32 @@ int bjp_batch_precondition(const bjp_csr_t *A, const bjp_batch_t *B, int precisi
     HIP_TRY(hipMemcpyAsync(off, P.off.data(), sizeof(int32_t) * P.off.size(), hipMemcpyHostToDevice, stream));
     hipLaunchKernelGGL(k_validate_batch, dim3(std::min(S, 4096)), dim3(kWG), 0, stream, S, rows,
                        A->row_ptr, A->col_idx, flags);
-    for (int s = 0; s < S; ++s) {
-        const SysInfo &si = P.sys[s];
-        SetupArgs sa{A->row_ptr, A->col_idx, A->val, off + P.off_base[s], si.nblocks,
-                     tiles + (size_t)si.tile0 * elem, flags, P.block_base[s]};
-        if (precision == BJP_FP32_STORE) launch_setup<float>(si.G, si.packets, sa, stream);
-        else launch_setup<double>(si.G, si.packets, sa, stream);
+    // one setup launch per lane-group width over all its systems' packets
+    std::vector<SetupSys> hi;
+    std::vector<int> cls_g, cls_begin, cls_packets;
+    for (int G = 1; G <= 64; G *= 2) {
+        const int begin = (int)hi.size();
+        int packets = 0;
+        for (int s = 0; s < S; ++s) {
+            const SysInfo &si = P.sys[s];
+            if (si.G != G) continue;
+            hi.push_back(SetupSys{P.off_base[s], si.tile0, si.nblocks, P.block_base[s], packets, 0});
+            packets += si.packets;
+        }
+        if (packets > 0) {
+            cls_g.push_back(G);
+            cls_begin.push_back(begin);
+            cls_packets.push_back(packets);
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(items, hi.data(), sizeof(SetupSys) * hi.size(), hipMemcpyHostToDevice, stream));
+    for (size_t c = 0; c < cls_g.size(); ++c) {
+        const int count = (c + 1 < cls_g.size() ? cls_begin[c + 1] : (int)hi.size()) - cls_begin[c];
+        const SetupArgs sa{A->row_ptr, A->col_idx, A->val, off, 0, tiles, flags, 0};
+        if (precision == BJP_FP32_STORE)
+            launch_setup_batch<float>(cls_g[c], cls_packets[c], sa, items + cls_begin[c], count, stream);
+        else
+            launch_setup_batch<double>(cls_g[c], cls_packets[c], sa, items + cls_begin[c], count, stream);
     }
     HIP_TRY(hipGetLastError());
     int32_t h[4];

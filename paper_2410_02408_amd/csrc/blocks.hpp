@@ -60,13 +60,14 @@ struct SetupArgs {
     int block_base;         // added to the reported block index (batches)
 };
 
+// Setup of packet pk (one wave).  Kernel bodies of k_setup / k_setup_reg,
+// shared with the batched setup, which finds each packet's system first.
 template <int G, typename TS>
-__global__ __launch_bounds__(64) void k_setup(SetupArgs a) {
+__device__ __forceinline__ void setup_lds_packet(const SetupArgs &a, int pk) {
     constexpr int P = 64 / G, LD = G + 1, E = packet_elems(G);
     __shared__ double T[P][G][LD];
     __shared__ double Wd[64];
     const int lane = threadIdx.x, g = lane / G, i = lane % G;
-    const int pk = blockIdx.x;
     const int t = pk * P + g;
     int s = 0, n = 0;
     if (t < a.nblocks) {
@@ -147,6 +148,11 @@ __global__ __launch_bounds__(64) void k_setup(SetupArgs a) {
     }
 }
 
+template <int G, typename TS>
+__global__ __launch_bounds__(64) void k_setup(SetupArgs a) {
+    setup_lds_packet<G, TS>(a, blockIdx.x);
+}
+
 // Value of v in lane l (l wave-uniform).
 __device__ __forceinline__ double lane_value(double v, int l) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
@@ -169,14 +175,14 @@ __device__ __forceinline__ double lane_value(double v, int l) {
 // them are zero) and keeps bounds tests out of the unrolled loops.  Measured
 // at 128^3, n_b = 64: 1.7 ms instead of 9.3 ms for the 32,768 blocks.
 template <int G, typename TS>
-__global__ __launch_bounds__(64) void k_setup_reg(SetupArgs a) {
+__device__ __forceinline__ void setup_reg_packet(const SetupArgs &a, int pk) {
     static_assert(G >= 8 && G <= 64 && (G & (G - 1)) == 0, "paired diagonals need G / 2 even");
     constexpr int P = 64 / G, LDM = G + 2, E = packet_elems(G);   // LDM: 16-byte aligned rows
     __shared__ __align__(16) double Mx[64][LDM];
     __shared__ __align__(16) double cb[2][64];
     __shared__ double Wd[64];
     const int lane = threadIdx.x, g = lane / G, i = lane % G, base = g * G;
-    const int t = blockIdx.x * P + g;
+    const int t = pk * P + g;
     int s = 0, n = 0;
     if (t < a.nblocks) {
         s = a.off[t];
@@ -261,7 +267,7 @@ __global__ __launch_bounds__(64) void k_setup_reg(SetupArgs a) {
 #pragma unroll
     for (int m = 0; m < G; ++m) Mx[lane][m] = w[m];
     __syncthreads();
-    TS *D = static_cast<TS *>(a.tiles) + (size_t)blockIdx.x * E;
+    TS *D = static_cast<TS *>(a.tiles) + (size_t)pk * E;
     typedef typename Pair<TS>::type TS2;
     auto diag = [&](int k) -> double {
         if (i >= n || 2 * k > n) return 0.0;
@@ -291,6 +297,11 @@ __global__ __launch_bounds__(64) void k_setup_reg(SetupArgs a) {
         }
         D[diag_index(G, G / 2, lane)] = (TS)v;
     }
+}
+
+template <int G, typename TS>
+__global__ __launch_bounds__(64) void k_setup_reg(SetupArgs a) {
+    setup_reg_packet<G, TS>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
