@@ -311,6 +311,7 @@ def mode_precision(args):
     deg = np.diff(A_h.row_ptr)
     res = {}
     for prec in ("fp64", "fp32"):
+        bjp.precondition(A, block_size=32, precision=prec)    # first use: kernel loading, allocation
         M, setup_ms = _timed(lambda: bjp.precondition(A, block_size=32, precision=prec))
         bjp.pcg_solve(A, M, b, workspace=ws)
         (x, info), ms = _timed(lambda: bjp.pcg_solve(A, M, b, workspace=ws))

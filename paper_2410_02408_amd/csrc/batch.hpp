@@ -131,6 +131,25 @@ __global__ __launch_bounds__(kWG) void k_apply_tiles(ApplyArgs a, TileSpan ts) {
     block_partial_at<2>(v, a.partials, ts.stride, t < ts.end ? t : -1);
 }
 
+// Start of a batch solve from x = 0, over the row tiles: x cleared, r = b
+// (b - A x with x = 0) and the partials the residual product would leave.
+__global__ __launch_bounds__(kWG) void k_start_zero_tiles(const double *b, double *x, double *r, double *partials,
+                                                          TileSpan ts) {
+    const int t = tile_of(ts);
+    double d = 0.0;
+    if (t < ts.end) {
+        const Tile tl = ts.tiles[t];
+        for (int i = tl.a0 + threadIdx.x; i < tl.a1; i += kWG) {
+            const double v = b[i];
+            x[i] = 0.0;
+            r[i] = v;
+            d += v * v;
+        }
+    }
+    const double v[2] = {d, d};
+    block_partial_at<2>(v, partials, ts.stride, t < ts.end ? t : -1);
+}
+
 // p_new = z + beta_s p_old over the rows of each active system.
 __global__ __launch_bounds__(kWG) void k_direction_tiles(PcgState *states, const double *z, double *p0,
                                                          double *p1, TileSpan ts) {

@@ -1145,7 +1145,13 @@ int pcg_solve_impl(const bjp_csr_t *A, const bjp_precond_t *M, const double *b, 
         }
         return panels ? Lf.grid : Ls.grid;
     };
-    finish<FIN_RESID_START>(fa, resid_product(0), stream);
+    if (o.x0_given) {
+        finish<FIN_RESID_START>(fa, resid_product(0), stream);
+    } else {
+        const int zgrid = round8(std::min(ceil_div(n, 8 * kWG), kMaxRedWG));
+        hipLaunchKernelGGL(k_start_zero, dim3(zgrid), dim3(kWG), 0, stream, b, r, partials, n);
+        finish<FIN_RESID_START>(fa, zgrid, stream);
+    }
     start_direction();
 
     // Polls overlap the iterations: the next batch is launched before the
@@ -1660,7 +1666,6 @@ int bjp_batch_pcg_solve(const bjp_csr_t *A, const bjp_batch_t *B, const bjp_batc
                        S, o.tol, capd);
     hipLaunchKernelGGL(k_fill, dim3(fill_grid), dim3(kWG), 0, stream, p0, A->n, 0.0);
     hipLaunchKernelGGL(k_fill, dim3(fill_grid), dim3(kWG), 0, stream, p1, A->n, 0.0);
-    hipLaunchKernelGGL(k_fill, dim3(fill_grid), dim3(kWG), 0, stream, x, A->n, 0.0);
 
     const TileSpan rows{tiles, 0, nrt, nrt, static_cast<const SysInfo *>(M->systems)};
     const int rgrid = round8(nrt);
@@ -1724,24 +1729,7 @@ int bjp_batch_pcg_solve(const bjp_csr_t *A, const bjp_batch_t *B, const bjp_batc
         apply_all(std::integral_constant<int, APPLY_UPDATE>{});
         hipLaunchKernelGGL(k_finish_sys<FIN_PCG_UPDATE>, dim3(S), dim3(kWG), 0, ls, fa, ptb, pte, npt);
     };
-    // The check_every iterations between polls are recorded once into a graph
-    // (on a private stream: the caller's may be the null stream, which cannot
-    // capture) and replayed on the caller's stream.  Every kernel reads its
-    // scalars from the device state, so one recording serves every replay.
-    // The graph holds kernel nodes only.
     GraphGuard gg;
-    if (!o.eager) {
-        HIP_TRY(hipStreamCreateWithFlags(&gg.cap, hipStreamNonBlocking));
-        HIP_TRY(hipStreamBeginCapture(gg.cap, hipStreamCaptureModeThreadLocal));
-        ls = gg.cap;
-        for (int c = 0; c < o.check_every; ++c) iteration();
-        ls = stream;
-        hipGraph_t g = nullptr;
-        HIP_TRY(hipStreamEndCapture(gg.cap, &g));
-        const hipError_t e = hipGraphInstantiate(&gg.exec, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        HIP_TRY(e);
-    }
     auto iterations = [&]() -> int {
         if (gg.exec) {
             HIP_TRY(hipGraphLaunch(gg.exec, stream));
@@ -1758,10 +1746,29 @@ int bjp_batch_pcg_solve(const bjp_csr_t *A, const bjp_batch_t *B, const bjp_batc
         return BJP_OK;
     };
 
-    sa.resid_phase = 0;
-    spmv_all(std::integral_constant<int, SPMV_RESID>{}, stream);
+    // x = 0: r = b without the residual product
+    hipLaunchKernelGGL(k_start_zero_tiles, dim3(rgrid), dim3(kWG), 0, stream, b, x, r, partials, rows);
     hipLaunchKernelGGL(k_finish_sys<FIN_RESID_START>, dim3(S), dim3(kWG), 0, stream, fa, rtb, rte, nrt);
     start_direction();
+
+    // The check_every iterations between polls are recorded once into a graph
+    // (on a private stream: the caller's may be the null stream, which cannot
+    // capture) and replayed on the caller's stream.  Every kernel reads its
+    // scalars from the device state, so one recording serves every replay.
+    // The graph holds kernel nodes only.  It is recorded after the start
+    // launches, so the GPU runs those meanwhile.
+    if (!o.eager) {
+        HIP_TRY(hipStreamCreateWithFlags(&gg.cap, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(gg.cap, hipStreamCaptureModeThreadLocal));
+        ls = gg.cap;
+        for (int c = 0; c < o.check_every; ++c) iteration();
+        ls = stream;
+        hipGraph_t g = nullptr;
+        HIP_TRY(hipStreamEndCapture(gg.cap, &g));
+        const hipError_t e = hipGraphInstantiate(&gg.exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIP_TRY(e);
+    }
 
     std::vector<int> repl(S, 0), host_status(S, BJP_OK);
     for (;;) {

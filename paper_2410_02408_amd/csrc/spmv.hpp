@@ -370,6 +370,20 @@ __global__ void k_x_finish_clear(PcgState *st) {
     if (threadIdx.x == 0) st->xpend = 0;
 }
 
+// Start of a solve from x = 0: the residual b - A x is b itself, so instead
+// of the residual product this copies b into r and leaves the partials that
+// product would (b^T b, r^T r), in its own per-workgroup layout.
+__global__ __launch_bounds__(kWG) void k_start_zero(const double *b, double *r, double *partials, int n) {
+    double d = 0.0;
+    for (int i = blockIdx.x * kWG + threadIdx.x; i < n; i += gridDim.x * kWG) {
+        const double v = b[i];
+        r[i] = v;
+        d += v * v;
+    }
+    const double v[2] = {d, d};
+    block_partial<2>(v, partials);
+}
+
 }  // namespace bjp
 
 namespace bjp {
