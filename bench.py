@@ -370,8 +370,8 @@ def mode_precision(args):
 def bandwidth_references(dev, gather_log2=()) -> dict:
     """What this GPU's memory system delivers for the solver's two access
     patterns, from the calibration kernels (calib/calib.hip): a read stream
-    over 2 GiB (the best of four grid sizes x 4, 8 or 16 loads in flight per
-    thread) and 2^27 random 8-byte gathers from regions of 2^k doubles."""
+    over 2 GiB (the best of five grid sizes, one to sixteen 256-thread
+    workgroups per compute unit, x 4, 8 or 16 loads in flight per thread) and 2^27 random 8-byte gathers from regions of 2^k doubles."""
     import ctypes as C
 
     import torch
@@ -386,7 +386,7 @@ def bandwidth_references(dev, gather_log2=()) -> dict:
     buf = torch.ones(1 << 28, dtype=torch.float64, device=dev)
     nbytes = buf.numel() * 8
     best = 0.0
-    for grid in (1024, 2048, 4096, 8192):
+    for grid in (256, 512, 1024, 2048, 4096):
         for inflight in (4, 8, 16):
             def run():
                 for _ in range(5):
@@ -518,7 +518,8 @@ def main():
         apply_avg_ms = float(np.mean(durs))
     achieved = per_launch / (apply_avg_ms * 1e-3) / 1e9
     iter_gbs = B_iter * sum(iters) / (sum(pcg_ms) / 1e3) / 1e9
-    traffic = read_traffic(f"apply_{args.workload}")
+    # the committed counters were taken on the FP64 application of this workload
+    traffic = read_traffic(f"apply_{args.workload}") if args.precision == "fp64" else None
     m_bytes = ab - 32 * W.A.n          # packed inverses + offsets
     kb_A = kappa_bytes(W.A.n, W.A.nnz, kA.steps, None)
     kb_M = kappa_bytes(W.A.n, W.A.nnz, kM.steps, m_bytes)
