@@ -418,7 +418,7 @@ def bandwidth_references(dev, gather_log2=()) -> dict:
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the solver runs on a single MI355X).", file=sys.stderr)
         sys.exit(2)
     if args.mode != "headline":
