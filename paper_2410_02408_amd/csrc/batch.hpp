@@ -95,11 +95,12 @@ template <int MODE>
 __global__ __launch_bounds__(kWG) void k_spmv_tiles_stream(SpmvArgs a, TileSpan ts) {
     const int t = tile_of(ts);
     double d0 = 0.0, d1 = 0.0;
+    __shared__ double prod[kStreamPer * kWG];
     if (t < ts.end) {
         const Tile tl = ts.tiles[t];
         const PcgState *st = a.st + tl.s;
         const bool run = (MODE == SPMV_RESID && a.resid_phase == 1) || !st->done;
-        if (run) spmv_stream_rows<MODE, true>(a, st->it, tl.a0, tl.a1, d0, d1);
+        if (run) spmv_stream_rows<MODE, true>(a, st->it, tl.a0, tl.a1, d0, d1, prod);
     }
     const double v[2] = {d0, d1};
     block_partial_at<2>(v, a.partials, ts.stride, t < ts.end ? t : -1);

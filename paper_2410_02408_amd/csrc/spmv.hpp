@@ -217,11 +217,13 @@ constexpr int kStreamRows = kWG;
 constexpr int kStreamCap = BJP_STREAM_CAP;
 constexpr int kStreamPer = kStreamCap / kWG;
 
+// prod: the caller's LDS stage of PER * kWG doubles (one array per kernel,
+// shared by the instantiations a kernel chooses between, so it is counted once
+// against the CU's LDS).
 template <int MODE, bool NT = false, int PER = kStreamPer, bool CD = false>
 __device__ __forceinline__ void spmv_stream_rows(const SpmvArgs &a, int it, int r0, int r1, double &d0,
-                                                 double &d1) {
+                                                 double &d1, double *prod) {
     constexpr int CAP = PER * kWG;   // entries per stage
-    __shared__ double prod[CAP];
     const int tid = threadIdx.x;
     const SpmvMode_<MODE> m(a, it);
     const int32_t *__restrict__ rp = a.rp;
@@ -294,8 +296,9 @@ __global__ __launch_bounds__(kWG) void k_spmv_stream(SpmvArgs a) {
     const int r0 = c * a.chunk;
     const int r1 = min(r0 + a.chunk, a.n);
     double d0 = 0.0, d1 = 0.0;
-    if (a.cd != nullptr && *a.cd_bad == 0) spmv_stream_rows<MODE, false, PER, true>(a, it, r0, r1, d0, d1);
-    else spmv_stream_rows<MODE, false, PER, false>(a, it, r0, r1, d0, d1);
+    __shared__ double prod[PER * kWG];
+    if (a.cd != nullptr && *a.cd_bad == 0) spmv_stream_rows<MODE, false, PER, true>(a, it, r0, r1, d0, d1, prod);
+    else spmv_stream_rows<MODE, false, PER, false>(a, it, r0, r1, d0, d1, prod);
     const double v[2] = {d0, d1};
     block_partial<2>(v, a.partials);
 }
