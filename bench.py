@@ -371,7 +371,8 @@ def bandwidth_references(dev, gather_log2=()) -> dict:
     """What this GPU's memory system delivers for the solver's two access
     patterns, from the calibration kernels (calib/calib.hip): a read stream
     over 2 GiB (the best of five grid sizes, one to sixteen 256-thread
-    workgroups per compute unit, x 4, 8 or 16 loads in flight per thread) and 2^27 random 8-byte gathers from regions of 2^k doubles."""
+    workgroups per compute unit, x 4, 8 or 16 loads in flight per thread) and
+    2^27 random 8-byte gathers from regions of 2^k doubles."""
     import ctypes as C
 
     import torch
