@@ -1,7 +1,8 @@
 """Control paths of the GPU solver against the oracle: residual replacement
 (Section 3.7's true-residual check, forced by tolerances below what the
 recursion alone can certify), the replacement budget, a replacement that
-falls due at max_iter, and partitions whose block size exceeds n."""
+falls due at max_iter, partitions whose block size exceeds n, and the start
+without a guess (r = b) against a start from x0 = 0."""
 import numpy as np
 import pytest
 import torch
@@ -123,3 +124,25 @@ def test_block_larger_than_system(gpu, orc, n, nb):
     ko = orc.kappa(A, b, 10, orc.Precond.uniform(A, nb))
     assert k.status == "OK" and k.steps == ko.steps == 1
     assert abs(k.kappa - 1.0) <= 1e-6 and abs(ko.kappa - 1.0) <= 1e-6
+
+
+@pytest.mark.parametrize("lanes", [-1, 4, -2], ids=["row-blocks", "lane-groups", "column-panels"])
+def test_zero_start_matches_zero_guess(gpu, orc, lanes):
+    """Without a starting guess the solve begins with r = b (no product); given
+    x0 = 0 it forms r = b - A x0 with the residual product of its schedule.
+    The two are the same iteration up to the order of the b^T b sum: the same
+    iteration count, solutions within rounding of each other and within the
+    parity bar of the oracle's."""
+    n = 5000
+    A_h = w.random_spd(n, np.random.default_rng(21))
+    b = w.rhs(n, 22)
+    A = dev(A_h)
+    M = gpu.precondition(A, block_size=32)
+    x1, i1 = gpu.pcg_solve(A, M, b, spmv_lanes=lanes)
+    x2, i2 = gpu.pcg_solve(A, M, b, x0=np.zeros(n), spmv_lanes=lanes)
+    ref = orc.pcg(A_h, b, orc.Precond.uniform(A_h, 32))
+    assert i1.status == i2.status == "OK"
+    assert i1.iterations == i2.iterations and abs(i1.iterations - ref.iterations) <= 1
+    x1, x2 = x1.cpu().numpy(), x2.cpu().numpy()
+    assert _rel(x1, x2) <= 1e-12
+    assert _rel(x1, ref.x) <= 1e-10
