@@ -186,15 +186,25 @@ __global__ void k_batch_restart(PcgState *states, const int *list, int count) {
     }
 }
 
-// Every column of a row must lie in the row's own system.
-__global__ void k_validate_batch(int S, const int32_t *sys_rows, const int32_t *rp, const int32_t *ci,
-                                 int32_t *flags) {
+// Every column of a row must lie in the row's own system.  A system's rows
+// are contiguous, so its entries are the contiguous range rp[lo] .. rp[hi] of
+// ci (row_ptr has been validated before this launch): one workgroup per
+// system scans that range coalesced, four loads in flight per thread.
+__global__ __launch_bounds__(kWG) void k_validate_batch(int S, const int32_t *sys_rows, const int32_t *rp,
+                                                        const int32_t *ci, int32_t *flags) {
     for (int s = blockIdx.x; s < S; s += gridDim.x) {
         const int lo = sys_rows[s], hi = sys_rows[s + 1];
+        const int e0 = rp[lo], e1 = rp[hi];
         bool bad = false;
-        for (int i = lo + threadIdx.x; i < hi; i += blockDim.x)
-            for (int k = rp[i]; k < rp[i + 1]; ++k)
-                if (ci[k] < lo || ci[k] >= hi) bad = true;
+        int k = e0 + threadIdx.x;
+        for (; k + 3 * kWG < e1; k += 4 * kWG) {
+            const int c0 = ci[k], c1 = ci[k + kWG], c2 = ci[k + 2 * kWG], c3 = ci[k + 3 * kWG];
+            bad |= c0 < lo || c0 >= hi || c1 < lo || c1 >= hi || c2 < lo || c2 >= hi || c3 < lo || c3 >= hi;
+        }
+        for (; k < e1; k += kWG) {
+            const int c = ci[k];
+            bad |= c < lo || c >= hi;
+        }
         if (bad) atomicOr(&flags[1], 1);
     }
 }

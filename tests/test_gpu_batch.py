@@ -88,6 +88,26 @@ def test_batch_rejects_coupled_systems(gpu):
     assert e.value.status == "EINVAL"
 
 
+@pytest.mark.parametrize("where", ["first", "middle", "last"])
+@pytest.mark.parametrize("side", ["below", "above"])
+def test_batch_rejects_column_just_outside(gpu, where, side):
+    """One entry of the middle system moved to the row just before or just
+    after that system's rows, at its first, a middle or its last entry (the
+    check scans each system's entries in rounds of four, then a tail)."""
+    mats, nbs, _ = small_batch(3, seed=7)
+    B = gpu.Batch.from_systems(mats, nbs, DEV)
+    rp = B.A.row_ptr.cpu().numpy()
+    lo, hi = int(B.sys_rows[1]), int(B.sys_rows[2])
+    e0, e1 = int(rp[lo]), int(rp[hi])
+    k = {"first": e0, "middle": (e0 + e1) // 2, "last": e1 - 1}[where]
+    ci = B.A.col_idx.clone()
+    ci[k] = lo - 1 if side == "below" else hi
+    bad = gpu.Batch(gpu.DeviceCsr(B.A.n, B.A.row_ptr, ci, B.A.val), B.sys_rows, B.block_sizes)
+    with pytest.raises(gpu.BjpError) as e:
+        gpu.batch_precondition(bad)
+    assert e.value.status == "EINVAL"
+
+
 def test_batch_not_spd_global_block_index(gpu):
     mats, _, _ = small_batch(3, seed=8)
     nbs = [16, 16, 16]
